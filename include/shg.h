@@ -1,0 +1,115 @@
+/*
+ * shg.h -- C ABI of libshg.so, the MI355X (gfx950) engine for contracted
+ * solid-harmonic-Gaussian (SHG) integrals.
+ *
+ * Reference: Golze, Benedikter, Iannuzzi, Wilhelm, Hutter, "Fast evaluation of
+ * solid harmonic Gaussian integrals for local resolution-of-the-identity
+ * methods and range-separated hybrid functionals" (arXiv:1701.06588).
+ *
+ * Conventions (all entry points):
+ *   - units: bohr and bohr^-2; FP64 in and out;
+ *   - a shell is one contracted function phi_{l,m} = N_l sum_alpha c_alpha
+ *     C_{l,m}(r) exp(-alpha r^2) (Sec. II.A, eqs. SHG_primitive, contracted_phi);
+ *     the caller passes RAW coefficients c_alpha, the library applies N_l
+ *     (eq. N_l), so results do not depend on the scale of c;
+ *   - real components m = -l..l stored at index m + l; m >= 0 is the cosine
+ *     and m < 0 the sine component (Sec. II.B, eq. Qref), i.e. the real solid
+ *     harmonic A_{l,|m|} R^{c/s}_{l,|m|}(r) (eq. A, Sec. II.F): p = (y, z, x);
+ *   - derivatives are with respect to the position of the first center,
+ *     d/dR_a (Sec. II.E, eq. dev_ab); d/dR_b = -d/dR_a by translation
+ *     invariance;
+ *   - every pointer argument below is a DEVICE pointer (allocated by the
+ *     caller, e.g. with torch) unless stated otherwise; the library never
+ *     frees caller memory;
+ *   - calls are asynchronous on the context's stream, except that the plain
+ *     entry points read back a few bytes (the class histogram and an error
+ *     flag) and therefore synchronise that stream once per call;
+ *   - return 0 on success, a negative SHG_E* code on error; no exception ever
+ *     crosses the ABI; shg_last_error() gives a message for the last failure.
+ */
+#ifndef SHG_H
+#define SHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHG_EINVAL  (-1)   /* bad argument (l, K, exponent, operator, omega, index, NULL) */
+#define SHG_ENOMEM  (-2)   /* device or host allocation failed */
+#define SHG_EDEVICE (-3)   /* HIP runtime error; text in shg_last_error() */
+
+#define SHG_LMAX_ORB 4     /* largest l of a two-center shell and of an orbital shell */
+#define SHG_LMAX_AUX 6     /* largest l of an auxiliary (RI) shell in shg_aab */
+#define SHG_KMAX     7     /* largest contraction length K of any shell */
+
+/* Operators O(r1 - r2) of the two-center integral (a|O|b), Sec. III and
+ * Table S1 of the supplement. omega is the range parameter. */
+typedef enum {
+    SHG_OVERLAP = 0,   /* delta(r)                       omega ignored */
+    SHG_COULOMB = 1,   /* 1/r                            omega ignored */
+    SHG_ERF     = 2,   /* erf(omega r)/r   (long range)   omega > 0    */
+    SHG_ERFC    = 3,   /* erfc(omega r)/r  (short range)  omega > 0    */
+    SHG_GAUSS   = 4    /* exp(-omega r^2)                 omega > 0    */
+} shg_op;
+
+/* Shell table. All arrays are DEVICE arrays of length nshell (prim arrays of
+ * length nprim_total); prim_off[i] is the first primitive of shell i. */
+typedef struct {
+    int32_t nshell;
+    int64_t nprim_total;
+    const double  *center;    /* [nshell][3]                                   */
+    const int32_t *l;         /* [nshell] 0..lmax                              */
+    const int32_t *nprim;     /* [nshell] 1..SHG_KMAX                          */
+    const int64_t *prim_off;  /* [nshell]                                      */
+    const double  *exps;      /* [nprim_total] > 0                             */
+    const double  *coefs;     /* [nprim_total] raw contraction coefficients    */
+} shg_shells;
+
+typedef struct shg_ctx shg_ctx;
+
+/* Create a context bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t, NULL = default stream). Uploads the Boys-function table.
+ * *ctx receives the handle (owned by the caller, release with shg_destroy). */
+int  shg_create(shg_ctx **ctx, void *hip_stream);
+void shg_destroy(shg_ctx *ctx);
+/* Message of the last failed call on ctx (static storage inside ctx; valid until
+ * the next call). ctx may be NULL (then: message of the last shg_create). */
+const char *shg_last_error(const shg_ctx *ctx);
+
+/* (a|O|b) for n shell pairs (Sec. II.B, eq. final_r12int_ab).
+ *   pairs   [n][2] int32   (shell a on center A, shell b on center B)
+ *   out_off [n]    int64   element offset of block i in out
+ *   out     block i = (2la+1) x (2lb+1) doubles row-major at out[out_off[i]]
+ * Shells must satisfy l <= SHG_LMAX_ORB, 1 <= K <= SHG_KMAX, exponents > 0;
+ * violations or pair indices outside [0, nshell) return SHG_EINVAL (no block
+ * of the call is then guaranteed). n == 0 is a no-op success. */
+int shg_pairs(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
+              const int32_t *pairs, int64_t n, const int64_t *out_off, double *out);
+
+/* (a|O|b) and d/dR_a (Sec. II.E, eq. dev_ab with the recurrences of
+ * Sec. II.F, eqs. cartesian_dev_x/y/z). Values as in shg_pairs; dout holds,
+ * for block i, three blocks (x, y, z) of (2la+1)(2lb+1) doubles starting at
+ * dout[3*out_off[i]]. */
+int shg_pairs_deriv(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
+                    const int32_t *pairs, int64_t n, const int64_t *out_off,
+                    double *out, double *dout);
+
+/* Three-index overlap (a b a~) (Sec. II.D, eq. aba_integrals): a = orb shell
+ * t[0] and a~ = aux shell t[1] share center A (their centers must be equal
+ * bit for bit, else SHG_EINVAL), b = orb shell t[2].
+ *   triples [n][3] int32
+ *   out     block i = (2la+1) x (2la~+1) x (2lb+1) doubles at out[out_off[i]]
+ *   dout    nullable; d/dR_A (a and a~ move together) as x, y, z blocks at
+ *           dout[3*out_off[i]]
+ * Orbital shells: l <= SHG_LMAX_ORB - 1 (= 3); aux shells: l <= SHG_LMAX_AUX. */
+int shg_aab(shg_ctx *ctx, const shg_shells *orb, const shg_shells *aux,
+            const int32_t *triples, int64_t n, const int64_t *out_off,
+            double *out, double *dout);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHG_H */

@@ -1,0 +1,466 @@
+// shg_math.h -- FP64 arithmetic of the SHG integral scheme for one shell pair
+// (or triple). Everything here is device code for gfx950; the functions are
+// also host-callable so that the unit tests can run the same arithmetic on the
+// CPU (SHG_HD expands to __host__ __device__ under hipcc and to nothing under a
+// plain C++ compiler).
+//
+// Method: Golze et al., arXiv:1701.06588.
+//   radial   (0_a|O|0_b)^(k), k-th derivative w.r.t. R_ab^2      Table S1
+//   contract O^(k)_{la,lb} = sum w_alpha w_beta (0|O|0)^(k)      eq. O_rab2_deriv
+//            with w_alpha = N_l c_alpha / (2 alpha)^l             eq. O_rab2, N_l
+//   angular  R^{c/s}_{l,m}(X), X = R_a - R_b                       eq. regular_scaled_harmonics_recursion
+//            W_{l,m,j,kappa}, Q = W_a W_b^T                         eqs. W_matrix, Q_matrix
+//   assemble (a|O|b) = sum_j O^(la+lb-j) Qtilde_j                 eqs. final_r12int_ab, Q_tilde
+//   deriv    eq. dev_ab with the lower-l recurrences               eqs. cartesian_dev_x/y/z
+//   (a b a~) Gaunt expansion + P^(k), eq. devsra2ms radial          Sec. II.D
+#pragma once
+
+#include <stdint.h>
+#include <math.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define SHG_HD __host__ __device__
+#define SHG_INL __forceinline__
+#else
+#define SHG_HD
+#define SHG_INL inline __attribute__((always_inline))
+#endif
+
+namespace shg {
+
+// ---------------------------------------------------------------------------
+// compile-time constants
+// ---------------------------------------------------------------------------
+constexpr double cfact(int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
+constexpr double cdfact(int n) { double f = 1; for (int i = n; i > 1; i -= 2) f *= i; return f; }  // n!!, (-1)!! = 1
+constexpr double csqrt(double x)
+{
+    if (x <= 0) return 0;
+    double g = x > 1 ? x : 1;
+    for (int i = 0; i < 200; ++i) g = 0.5 * (g + x / g);
+    return g;
+}
+constexpr double cpow2(int n) { double f = 1; for (int i = 0; i < n; ++i) f *= 2; return f; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cabs(int a) { return a < 0 ? -a : a; }
+
+// A_{l,m} = (-1)^m sqrt((2 - delta_m0)(l+|m|)!(l-|m|)!)   (eq. A; A_{l,-1} = A_{l,1})
+constexpr double A_lm(int l, int m)
+{
+    int mu = cabs(m);
+    double s = csqrt((mu == 0 ? 1.0 : 2.0) * cfact(l + mu) * cfact(l - mu));
+    return (mu & 1) ? -s : s;
+}
+// B_{j,kappa} = 1 / ((2 - delta_kappa0)(j+kappa)!(j-kappa)!)   (eq. B)
+constexpr double B_jk(int j, int k) { return 1.0 / ((k == 0 ? 1.0 : 2.0) * cfact(j + k) * cfact(j - k)); }
+
+constexpr double PI = 3.141592653589793238462643383279502884;
+constexpr double PI_1_5 = 5.568327996831707845284817982118835702;    // pi^(3/2)
+constexpr double PI_2_5 = 17.493418327624862846262821679872926940;   // pi^(5/2)
+constexpr double PI_3 = 31.006276680299820175476315067101395202;     // pi^3
+
+// ---------------------------------------------------------------------------
+// Boys function F_n(T) = int_0^1 exp(-T t^2) t^(2n) dt  (supplement eq. 3)
+// T < BOYS_TMAX: 8-term Taylor expansion of F_nhi about the nearest grid point
+//   (spacing 1/16, |dT| <= 1/32, dF_n/dT = -F_{n+1}, supplement eq. 4), then
+//   the downward recurrence F_n = (2T F_{n+1} + e^-T) / (2n+1);
+// T >= BOYS_TMAX: F_0 = sqrt(pi/T)/2 (erf(sqrt T) = 1 to double precision for
+//   T >= 36) and the upward recurrence F_{n+1} = ((2n+1) F_n - e^-T) / (2T),
+//   stable there because (2n+1)/(2T) < 1.
+// ---------------------------------------------------------------------------
+constexpr int BOYS_NTAB = 17;          // tabulated orders 0..16
+constexpr int BOYS_STRIDE = 17;
+constexpr int BOYS_PER_UNIT = 16;      // grid points per unit of T
+constexpr double BOYS_TMAX = 36.0;
+constexpr int BOYS_NPTS = 36 * 16 + 2;
+constexpr int BOYS_TAYLOR = 8;
+
+template <int NLO, int NHI>
+SHG_HD SHG_INL void boys(double T, const double *__restrict__ tab, double (&F)[NHI - NLO + 1])
+{
+    static_assert(NHI + BOYS_TAYLOR - 1 < BOYS_NTAB, "Boys table too short");
+    double e = exp(-T);
+    if (T < BOYS_TMAX) {
+        int i = (int)(T * BOYS_PER_UNIT + 0.5);
+        double d = T - i * (1.0 / BOYS_PER_UNIT);
+        const double *row = tab + (size_t)i * BOYS_STRIDE + NHI;
+        double acc = row[BOYS_TAYLOR - 1];
+#pragma unroll
+        for (int k = BOYS_TAYLOR - 2; k >= 0; --k) acc = fma(acc, -d * (1.0 / (k + 1)), row[k]);
+        F[NHI - NLO] = acc;
+        double tt = 2 * T;
+#pragma unroll
+        for (int n = NHI - 1; n >= NLO; --n) F[n - NLO] = fma(tt, F[n + 1 - NLO], e) * (1.0 / (2 * n + 1));
+    } else {
+        double inv2t = 0.5 / T;
+        double f = 0.5 * sqrt(PI / T);
+        if (NLO == 0) F[0] = f;
+#pragma unroll
+        for (int n = 0; n < NHI; ++n) {
+            f = ((2 * n + 1) * f - e) * inv2t;
+            if (n + 1 >= NLO) F[n + 1 - NLO] = f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// s-s integrals and their R^2 derivatives, Table S1 (k = KLO..KHI)
+// ---------------------------------------------------------------------------
+enum { OP_OVERLAP = 0, OP_COULOMB = 1, OP_ERF = 2, OP_ERFC = 3, OP_GAUSS = 4 };
+
+template <int OP, int KLO, int KHI>
+SHG_HD SHG_INL void radial(double a, double b, double R2, double omega, const double *__restrict__ tab,
+                           double (&g)[KHI - KLO + 1])
+{
+    constexpr int NK = KHI - KLO + 1;
+    double p = a + b, ip = 1.0 / p, rho = a * b * ip, T = rho * R2;
+    if (OP == OP_OVERLAP || OP == OP_GAUSS) {
+        double pre, fac;
+        if (OP == OP_OVERLAP) {
+            pre = PI_1_5 * ip * sqrt(ip) * exp(-T);
+            fac = -rho;
+        } else {
+            double q = rho + omega, iq = 1.0 / q, u = ip * iq;
+            pre = PI_3 * u * sqrt(u) * exp(-omega * T * iq);
+            fac = -omega * rho * iq;
+        }
+        double f = pre;
+#pragma unroll
+        for (int k = 0; k < KLO; ++k) f *= fac;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) { g[k] = f; f *= fac; }
+    } else {
+        double pre = 2.0 * PI_2_5 / (a * b * sqrt(p));
+        double Fc[NK];
+        if (OP == OP_COULOMB || OP == OP_ERFC) {
+            boys<KLO, KHI>(T, tab, Fc);
+            double f = pre;
+#pragma unroll
+            for (int k = 0; k < KLO; ++k) f *= -rho;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) { g[k] = f * Fc[k]; f *= -rho; }
+        }
+        if (OP == OP_ERF || OP == OP_ERFC) {
+            double w2 = omega * omega, s = w2 / (w2 + rho);
+            double Fe[NK];
+            boys<KLO, KHI>(T * s, tab, Fe);
+            double fac = -rho * s, f = pre * sqrt(s);
+#pragma unroll
+            for (int k = 0; k < KLO; ++k) f *= fac;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                double v = f * Fe[k];
+                g[k] = (OP == OP_ERF) ? v : g[k] - v;
+                f *= fac;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// regular scaled solid harmonics R^{c/s}_{l,m}(X), 0 <= m <= l <= L
+// (eq. regular_scaled_harmonics_recursion; the three-term step is used for
+// 0 <= m <= l with R_{l-1,m} = 0 when m > l-1)
+// ---------------------------------------------------------------------------
+constexpr int ridx(int l, int m) { return l * (l + 1) / 2 + m; }
+
+template <int L>
+struct RTab {
+    double c[(L + 1) * (L + 2) / 2];
+    double s[(L + 1) * (L + 2) / 2];
+};
+
+template <int L>
+SHG_HD SHG_INL void solid_R(double x, double y, double z, RTab<L> &R)
+{
+    double r2 = x * x + y * y + z * z;
+    R.c[0] = 1.0;
+    R.s[0] = 0.0;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        double inv = 1.0 / (2 * l + 2);
+        R.c[ridx(l + 1, l + 1)] = -(x * R.c[ridx(l, l)] - y * R.s[ridx(l, l)]) * inv;
+        R.s[ridx(l + 1, l + 1)] = -(y * R.c[ridx(l, l)] + x * R.s[ridx(l, l)]) * inv;
+#pragma unroll
+        for (int m = 0; m <= l; ++m) {
+            double den = 1.0 / ((l + m + 1) * (l - m + 1));
+            double zc = (2 * l + 1) * z * R.c[ridx(l, m)];
+            if (m <= l - 1) zc -= r2 * R.c[ridx(l - 1, m)];
+            R.c[ridx(l + 1, m)] = zc * den;
+            if (m == 0) {
+                R.s[ridx(l + 1, 0)] = 0.0;
+            } else {
+                double zs = (2 * l + 1) * z * R.s[ridx(l, m)];
+                if (m <= l - 1) zs -= r2 * R.s[ridx(l - 1, m)];
+                R.s[ridx(l + 1, m)] = zs * den;
+            }
+        }
+    }
+}
+
+// presence of R^{c/s}_{l,m} (signed m): zero outside |m| <= l; R^s_{l,0} = 0
+constexpr bool rc_nz(int l, int m) { return l >= 0 && cabs(m) <= l; }
+constexpr bool rs_nz(int l, int m) { return l >= 0 && cabs(m) <= l && m != 0; }
+
+// R^c_{l,-m} = (-1)^m R^c_{l,m},  R^s_{l,-m} = -(-1)^m R^s_{l,m}
+template <int L>
+SHG_HD SHG_INL double Rc(const RTab<L> &R, int l, int m)
+{
+    int mu = cabs(m);
+    double v = R.c[ridx(l, mu)];
+    return (m < 0 && (mu & 1)) ? -v : v;
+}
+template <int L>
+SHG_HD SHG_INL double Rs(const RTab<L> &R, int l, int m)
+{
+    int mu = cabs(m);
+    double v = R.s[ridx(l, mu)];
+    return (m < 0 && !(mu & 1)) ? -v : v;
+}
+
+// ---------------------------------------------------------------------------
+// Real translation matrix W_{l,m,j,kappa} (eq. W_matrix), evaluated with the
+// solid harmonics at X = R_a - R_b: Q(R_ab) = W(-R_ab) W^T(-R_ab) (eq. Q_matrix)
+// and W(R_ab) takes its harmonics at -R_ab, so the two negations cancel.
+// Row t (0 = c, 1 = s), column s (0 = c, 1 = s): W[c][c], W[c][s], W[s][c], W[s][s].
+// Absent terms are dropped at compile time (all indices are constants once the
+// caller's loops are unrolled).
+// ---------------------------------------------------------------------------
+constexpr bool w_nz(int l, int m, int j, int k)
+{
+    return l >= 0 && j <= l && (rc_nz(l - j, m - k) || rc_nz(l - j, m + k));
+}
+
+// sum of +-R terms with compile-time presence: s1*R(l,m1) + s2*R(l,m2)
+template <int L>
+SHG_HD SHG_INL double rc_comb(const RTab<L> &R, int l, int m1, double s1, int m2, double s2)
+{
+    bool p1 = rc_nz(l, m1), p2 = rc_nz(l, m2);
+    if (p1 && p2) return s2 > 0 ? s1 * Rc(R, l, m1) + Rc(R, l, m2) : s1 * Rc(R, l, m1) - Rc(R, l, m2);
+    if (p1) return s1 * Rc(R, l, m1);
+    if (p2) return s2 * Rc(R, l, m2);
+    return 0.0;
+}
+template <int L>
+SHG_HD SHG_INL double rs_comb(const RTab<L> &R, int l, int m1, double s1, int m2, double s2)
+{
+    bool p1 = rs_nz(l, m1), p2 = rs_nz(l, m2);
+    if (p1 && p2) return s2 > 0 ? s1 * Rs(R, l, m1) + Rs(R, l, m2) : s1 * Rs(R, l, m1) - Rs(R, l, m2);
+    if (p1) return s1 * Rs(R, l, m1);
+    if (p2) return s2 * Rs(R, l, m2);
+    return 0.0;
+}
+// is entry (t, s) of W_{l,m,j,k} structurally non-zero?
+constexpr bool wentry_nz(int l, int m, int j, int k, int t, int s)
+{
+    // column s = 1 (cs, ss) vanishes for kappa = 0; row t = 1 at m = 0 vanishes
+    if (s == 1 && k == 0) return false;
+    if (t == 1 && m == 0) return false;
+    int lj = l - j;
+    bool use_c = (t == s);   // cc and ss use R^c, cs and sc use R^s
+    return use_c ? (rc_nz(lj, m - k) || rc_nz(lj, m + k)) : (rs_nz(lj, m - k) || rs_nz(lj, m + k));
+}
+
+template <int L>
+SHG_HD SHG_INL double wentry(const RTab<L> &R, int l, int m, int j, int k, int t, int s)
+{
+    int lj = l - j;
+    double sg = (k & 1) ? -1.0 : 1.0;
+    double half = (k == 0) ? 0.5 : 1.0;
+    if (t == 0 && s == 0) return half * rc_comb(R, lj, m - k, 1.0, m + k, sg);     // W^cc
+    if (t == 0 && s == 1) return rs_comb(R, lj, m - k, -1.0, m + k, sg);           // W^cs
+    if (t == 1 && s == 0) return half * rs_comb(R, lj, m - k, 1.0, m + k, sg);     // W^sc
+    return rc_comb(R, lj, m - k, 1.0, m + k, -sg);                                 // W^ss
+}
+
+// ---------------------------------------------------------------------------
+// compile-time loop
+// ---------------------------------------------------------------------------
+template <int V>
+struct IC {
+    static constexpr int value = V;
+};
+template <int B, int E, class F>
+SHG_HD SHG_INL void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(IC<B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Qhat^{ta,tb}_{la,ma,lb,mb,j} = (-1)^lb 2^(la+lb-j) (2j-1)!! sum_kappa B_{j,kappa}
+//                                 Q^{ta,tb}_{la,ma,lb,mb,j,kappa}
+// i.e. Qtilde of eq. Q_tilde without the factor A_{la,ma} A_{lb,mb}. ma, mb are
+// signed (the derivative recurrences reach m = -1), t = 0 cosine, 1 sine.
+// ---------------------------------------------------------------------------
+constexpr bool qhat_nz(int la, int ma, int ta, int lb, int mb, int tb, int j)
+{
+    if (la < 0 || lb < 0 || j < 0 || j > cmin(la, lb)) return false;
+    if (cabs(ma) > la || cabs(mb) > lb) return false;
+    if ((ta == 1 && ma == 0) || (tb == 1 && mb == 0)) return false;
+    for (int k = 0; k <= j; ++k)
+        for (int s = 0; s < 2; ++s)
+            if (wentry_nz(la, ma, j, k, ta, s) && wentry_nz(lb, mb, j, k, tb, s)) return true;
+    return false;
+}
+
+template <int LA, int MA, int TA, int LB, int MB, int TB, int J, int L>
+SHG_HD SHG_INL double qhat(const RTab<L> &R)
+{
+    constexpr double pref = ((LB & 1) ? -1.0 : 1.0) * cpow2(LA + LB - J) * cdfact(2 * J - 1);
+    double acc = 0.0;
+    bool first = true;
+    static_for<0, J + 1>([&](auto KK) {
+        constexpr int K = decltype(KK)::value;
+        static_for<0, 2>([&](auto SS) {
+            constexpr int S = decltype(SS)::value;
+            if constexpr (wentry_nz(LA, MA, J, K, TA, S) && wentry_nz(LB, MB, J, K, TB, S)) {
+                constexpr double c = pref * B_jk(J, K);
+                double t = c * wentry(R, LA, MA, J, K, TA, S) * wentry(R, LB, MB, J, K, TB, S);
+                acc = first ? t : acc + t;
+                first = false;
+            }
+        });
+    });
+    return acc;
+}
+
+// adds sgn * Qhat(...) to acc when the term is structurally non-zero
+template <int LA, int MA, int TA, int LB, int MB, int TB, int J, int L>
+SHG_HD SHG_INL void qhat_acc(const RTab<L> &R, double sgn, double &acc)
+{
+    if constexpr (qhat_nz(LA, MA, TA, LB, MB, TB, J)) acc = fma(sgn, qhat<LA, MA, TA, LB, MB, TB, J>(R), acc);
+}
+
+// ---------------------------------------------------------------------------
+// Shell preparation: N_l (eq. N_l) and the folded weights
+// w_alpha = N_l c_alpha / (2 alpha)^l (eq. O_rab2).
+// ---------------------------------------------------------------------------
+SHG_HD SHG_INL double shell_norm(int l, int K, const double *e, const double *c)
+{
+    // N_l = K_l [ sum pi^(1/2) (2l+2)! c c' / (2^(2l+3) (l+1)! (a+a')^(l+3/2)) ]^(-1/2)
+    double f2l2 = 1, fl1 = 1, p2 = 1;
+    for (int i = 2; i <= 2 * l + 2; ++i) f2l2 *= i;
+    for (int i = 2; i <= l + 1; ++i) fl1 *= i;
+    for (int i = 0; i < 2 * l + 3; ++i) p2 *= 2;
+    double s = 0;
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j) {
+            double ab = e[i] + e[j];
+            double pw = ab;
+            for (int q = 0; q < l; ++q) pw *= ab;
+            s += c[i] * c[j] / (pw * sqrt(ab));
+        }
+    s *= sqrt(PI) * f2l2 / (p2 * fl1);
+    double Kl = sqrt((2 * l + 1) / (4 * PI));
+    return Kl / sqrt(s);
+}
+
+// ---------------------------------------------------------------------------
+// Contraction of the radial terms for one shell pair (eq. O_rab2_deriv):
+// O^(k) = sum_{alpha,beta} w_alpha w_beta (0|O|0)^(k), k = KLO..KHI with
+// KLO = max(la,lb), KHI = la+lb (+1 with derivatives).
+// ---------------------------------------------------------------------------
+template <int LA, int LB, bool D>
+struct PairK {
+    static constexpr int KLO = cmax(LA, LB), KHI = LA + LB + (D ? 1 : 0), NK = KHI - KLO + 1;
+};
+
+template <int LA, int LB, int OP, bool D>
+SHG_HD SHG_INL void contract_pair(const double *__restrict__ ea, const double *__restrict__ wa, int ka,
+                                  const double *__restrict__ eb, const double *__restrict__ wb, int kb,
+                                  double R2, double omega, const double *__restrict__ tab,
+                                  double (&O)[PairK<LA, LB, D>::NK])
+{
+    using PK = PairK<LA, LB, D>;
+#pragma unroll
+    for (int k = 0; k < PK::NK; ++k) O[k] = 0.0;
+    for (int i = 0; i < ka; ++i) {
+        double a = ea[i], w1 = wa[i];
+        for (int j = 0; j < kb; ++j) {
+            double g[PK::NK];
+            radial<OP, PK::KLO, PK::KHI>(a, eb[j], R2, omega, tab, g);
+            double ww = w1 * wb[j];
+#pragma unroll
+            for (int k = 0; k < PK::NK; ++k) O[k] = fma(ww, g[k], O[k]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One block row (fixed m_a = IA - LA) of (a|O|b) and, with D, of d/dR_a:
+//   value  = A_a A_b sum_j O^(la+lb-j) Qhat_j                    eq. final_r12int_ab
+//   d/dR_i = A_a A_b [ 2 X_i sum_j O^(la+lb-j+1) Qhat_j
+//                      + sum_j O^(la+lb-j) dQhat_j/dR_i ]          eq. dev_ab
+// with dQtilde/dR_i from (l-1) terms, eqs. cartesian_dev_x/y/z (with the
+// factor A_a A_b taken out, the ratios of A's there reduce to 1).
+// out_row / dout_row point at element (IA, 0) of the block; dstride = SZ.
+// ---------------------------------------------------------------------------
+template <int LA, int LB, int IA, bool D, int L>
+SHG_HD SHG_INL void pair_row(const RTab<L> &R, const double *O, const double X[3],
+                             double *__restrict__ out_row, double *__restrict__ dout_row, int dstride)
+{
+    using PK = PairK<LA, LB, D>;
+    constexpr int JM = cmin(LA, LB), NB = 2 * LB + 1;
+    constexpr int MA = IA - LA, MUA = cabs(MA), TA = MA < 0 ? 1 : 0;
+    constexpr double SA = TA ? -1.0 : 1.0;
+    static_for<0, NB>([&](auto IBB) {
+        constexpr int IB = decltype(IBB)::value;
+        constexpr int MB = IB - LB, MUB = cabs(MB), TB = MB < 0 ? 1 : 0;
+        constexpr double SB = TB ? -1.0 : 1.0;
+        constexpr double AA = A_lm(LA, MUA) * A_lm(LB, MUB);
+        double v = 0.0, v1 = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
+        static_for<0, JM + 1>([&](auto JJ) {
+            constexpr int J = decltype(JJ)::value;
+            constexpr int K0 = LA + LB - J - PK::KLO;
+            if constexpr (qhat_nz(LA, MUA, TA, LB, MUB, TB, J)) {
+                double q = qhat<LA, MUA, TA, LB, MUB, TB, J>(R);
+                v = fma(O[K0], q, v);
+                if constexpr (D) v1 = fma(O[K0 + 1], q, v1);
+            }
+            if constexpr (D) {
+                double tx = 0.0, ty = 0.0, tz = 0.0;
+                qhat_acc<LA - 1, MUA + 1, TA, LB, MUB, TB, J>(R, 1.0, tx);
+                qhat_acc<LA - 1, MUA - 1, TA, LB, MUB, TB, J>(R, -1.0, tx);
+                qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, TB, J>(R, -1.0, tx);
+                qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, TB, J>(R, 1.0, tx);
+                qhat_acc<LA - 1, MUA + 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
+                qhat_acc<LA - 1, MUA - 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
+                qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, 1 - TB, J>(R, -SB, ty);
+                qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, 1 - TB, J>(R, -SB, ty);
+                qhat_acc<LA - 1, MUA, TA, LB, MUB, TB, J>(R, 2.0, tz);
+                qhat_acc<LA, MUA, TA, LB - 1, MUB, TB, J>(R, -2.0, tz);
+                dx = fma(O[K0], tx, dx);
+                dy = fma(O[K0], ty, dy);
+                dz = fma(O[K0], tz, dz);
+            }
+        });
+        out_row[IB] = AA * v;
+        if constexpr (D) {
+            double t1 = 2.0 * v1;
+            dout_row[IB] = AA * fma(t1, X[0], dx);
+            dout_row[dstride + IB] = AA * fma(t1, X[1], dy);
+            dout_row[2 * dstride + IB] = AA * fma(t1, X[2], dz);
+        }
+    });
+}
+
+// whole block (host-side use and small classes): all rows
+template <int LA, int LB, bool D>
+SHG_HD SHG_INL void pair_block_from_O(const double *O, const double X[3], double *__restrict__ out,
+                                      double *__restrict__ dout)
+{
+    constexpr int NB = 2 * LB + 1, SZ = (2 * LA + 1) * NB;
+    RTab<cmax(LA, LB)> R;
+    solid_R<cmax(LA, LB)>(X[0], X[1], X[2], R);
+    static_for<0, 2 * LA + 1>([&](auto IAA) {
+        constexpr int IA = decltype(IAA)::value;
+        pair_row<LA, LB, IA, D>(R, O, X, out + IA * NB, D ? dout + IA * NB : nullptr, SZ);
+    });
+}
+
+}  // namespace shg

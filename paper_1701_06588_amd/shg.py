@@ -1,0 +1,146 @@
+"""Thin ctypes binding of libshg.so (C ABI in include/shg.h).
+
+Argument marshalling only: torch supplies device memory and the stream, every
+step of the integral path runs in the library's HIP kernels. There is no CPU
+fallback: if the library or a GPU is missing, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshg.so")
+
+OPS = {"overlap": 0, "coulomb": 1, "erf": 2, "erfc": 3, "gauss": 4}
+ERRORS = {-1: "SHG_EINVAL", -2: "SHG_ENOMEM", -3: "SHG_EDEVICE"}
+EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pairs_deriv", "shg_aab")
+
+
+class ShgShells(C.Structure):
+    _fields_ = [("nshell", C.c_int32), ("nprim_total", C.c_int64), ("center", C.c_void_p),
+                ("l", C.c_void_p), ("nprim", C.c_void_p), ("prim_off", C.c_void_p),
+                ("exps", C.c_void_p), ("coefs", C.c_void_p)]
+
+
+class ShgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libshg.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1701_06588_amd/build.py")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.shg_create.argtypes = [C.POINTER(C.c_void_p), P]
+    lib.shg_create.restype = C.c_int
+    lib.shg_destroy.argtypes = [P]
+    lib.shg_destroy.restype = None
+    lib.shg_last_error.argtypes = [P]
+    lib.shg_last_error.restype = C.c_char_p
+    lib.shg_pairs.argtypes = [P, C.POINTER(ShgShells), C.c_int, C.c_double, P, C.c_int64, P, P]
+    lib.shg_pairs.restype = C.c_int
+    lib.shg_pairs_deriv.argtypes = [P, C.POINTER(ShgShells), C.c_int, C.c_double, P, C.c_int64, P, P, P]
+    lib.shg_pairs_deriv.restype = C.c_int
+    lib.shg_aab.argtypes = [P, C.POINTER(ShgShells), C.POINTER(ShgShells), P, C.c_int64, P, P, P]
+    lib.shg_aab.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class DeviceShells:
+    """A shell table resident in device memory (torch tensors) plus its C view."""
+
+    def __init__(self, sh, device):
+        import torch
+        self.center = torch.as_tensor(np.ascontiguousarray(sh.center, np.float64), device=device)
+        self.l = torch.as_tensor(np.ascontiguousarray(sh.l, np.int32), device=device)
+        self.nprim = torch.as_tensor(np.ascontiguousarray(sh.nprim, np.int32), device=device)
+        self.prim_off = torch.as_tensor(np.ascontiguousarray(sh.prim_off, np.int64), device=device)
+        self.exps = torch.as_tensor(np.ascontiguousarray(sh.exps, np.float64), device=device)
+        self.coefs = torch.as_tensor(np.ascontiguousarray(sh.coefs, np.float64), device=device)
+        self.host = sh
+        self.c = ShgShells(int(sh.n), int(len(sh.exps)), _ptr(self.center), _ptr(self.l), _ptr(self.nprim),
+                           _ptr(self.prim_off), _ptr(self.exps), _ptr(self.coefs))
+
+
+class Engine:
+    """One shg_ctx bound to the current device and a torch stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libshg needs a ROCm GPU; none is visible")
+        self.lib = load_library()
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = self.lib.shg_create(C.byref(h), C.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise ShgError(rc, self.lib.shg_last_error(None).decode())
+        self.ctx = h
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.shg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise ShgError(rc, self.lib.shg_last_error(self.ctx).decode())
+
+    def shells(self, sh) -> DeviceShells:
+        return DeviceShells(sh, self.torch.device("cuda", self.torch.cuda.current_device()))
+
+    def pairs(self, dsh: DeviceShells, op: str, omega: float, pairs, out_off, out, dout=None):
+        """shg_pairs / shg_pairs_deriv on device tensors (pairs int32 [n,2], out_off int64 [n])."""
+        n = int(pairs.shape[0])
+        if dout is None:
+            rc = self.lib.shg_pairs(self.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs), n,
+                                    _ptr(out_off), _ptr(out))
+        else:
+            rc = self.lib.shg_pairs_deriv(self.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs), n,
+                                          _ptr(out_off), _ptr(out), _ptr(dout))
+        self._check(rc)
+
+    def aab(self, orb: DeviceShells, aux: DeviceShells, triples, out_off, out, dout=None):
+        n = int(triples.shape[0])
+        rc = self.lib.shg_aab(self.ctx, C.byref(orb.c), C.byref(aux.c), _ptr(triples), n, _ptr(out_off),
+                              _ptr(out), _ptr(dout))
+        self._check(rc)
+
+
+def run_workload_pairs(engine: Engine, w, op: str, deriv: bool):
+    """Upload a workload, evaluate one operator, return host numpy (out, dout)."""
+    torch = engine.torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    dsh = engine.shells(w.shells)
+    off, tot = w.out_offsets()
+    pairs = torch.as_tensor(np.ascontiguousarray(w.pairs, np.int32), device=dev)
+    out_off = torch.as_tensor(off, device=dev)
+    out = torch.full((max(tot, 1),), float("nan"), dtype=torch.float64, device=dev)
+    dout = torch.full((max(3 * tot, 1),), float("nan"), dtype=torch.float64, device=dev) if deriv else None
+    engine.pairs(dsh, op, w.omega.get(op, 0.0), pairs, out_off, out, dout)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()[:tot], (dout.cpu().numpy()[:3 * tot] if deriv else None)
