@@ -109,6 +109,41 @@ int shg_aab(shg_ctx *ctx, const shg_shells *orb, const shg_shells *aux,
             const int32_t *triples, int64_t n, const int64_t *out_off,
             double *out, double *dout);
 
+/* ---- tuning and timing ------------------------------------------------- */
+
+/* Tile shape used by the per-class launches of operator op for class
+ * (la, lb, deriv): tp shell pairs per workgroup (64, 128 or 256; 256/tp lanes
+ * share the radial work of one pair) and rows_pp block rows per LDS staging
+ * pass (1..2la+1). Returns SHG_EINVAL for values outside those ranges or tiles
+ * needing more than 160 KiB of LDS. Host pointers for the get variant. */
+int shg_set_tile_shape(shg_ctx *ctx, int op, int la, int lb, int deriv, int tp, int rows_pp);
+int shg_get_tile_shape(const shg_ctx *ctx, int op, int la, int lb, int deriv, int *tp, int *rows_pp);
+
+/* Autotuner: bins the caller's pair list like shg_pairs(_deriv) (dout NULL:
+ * values only), then for every class present times each admissible tile shape
+ * `reps` times with HIP events and keeps the fastest for (op, class, deriv).
+ * Synchronous. On return out/dout hold the results computed with the selected
+ * shapes. Arguments and errors as in shg_pairs_deriv. */
+int shg_autotune(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
+                 const int32_t *pairs, int64_t n, const int64_t *out_off,
+                 double *out, double *dout, int reps);
+/* Tuning cache (host path): JSON list of the tuned shapes with the GPU
+ * architecture name; load applies only entries of the current architecture
+ * and returns how many it applied (or SHG_EINVAL if the file is unreadable). */
+int shg_tuning_save(const shg_ctx *ctx, const char *path);
+int shg_tuning_load(shg_ctx *ctx, const char *path);
+
+/* Per-launch timing with HIP events recorded on the context stream around
+ * every class launch of shg_pairs / shg_pairs_deriv (profiled calls also
+ * synchronise at their end). shg_profile_enable clears the counters.
+ * shg_profile_read returns, for class (la, lb, deriv), the accumulated kernel
+ * milliseconds, the number of launches and the pairs they processed; la < 0
+ * selects the binning stage (shell preparation, classification, scan,
+ * scatter) instead. Host pointers. */
+int shg_profile_enable(shg_ctx *ctx, int on);
+int shg_profile_read(const shg_ctx *ctx, int la, int lb, int deriv, double *ms, int64_t *launches,
+                     int64_t *pairs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,16 @@ struct shg_ctx {
     double *w2 = nullptr; size_t w2_cap = 0;         // second shell table (aab aux)
     int32_t *keys = nullptr; size_t keys_cap = 0;
     int32_t *order = nullptr; size_t order_cap = 0;
-    double *Obuf = nullptr; size_t Obuf_cap = 0;
+    TileShape shape[5][LMAX + 1][LMAX + 1][2];      // tile shape per (op, la, lb, deriv), autotuned
+    char arch[64] = {0};
+    double tune_ms[5][LMAX + 1][LMAX + 1][2] = {};
+    // optional per-launch timing with HIP events (shg_profile_*)
+    int prof_on = 0;
+    hipEvent_t ev[NCLASS + 3] = {};   // [0] binning start, [1] binning end, [2+cls], [NCLASS+2] classes start
+    double prof_ms[NCLASS][2] = {};
+    int64_t prof_launches[NCLASS][2] = {}, prof_pairs[NCLASS][2] = {};
+    double prof_bin_ms = 0;
+    int64_t prof_bin_calls = 0;
     int32_t *bins = nullptr;         // [2][NBINS_MAX + 1]: histogram, then cursors
     int32_t *err = nullptr;          // device error flag
     int32_t *host_rb = nullptr;      // pinned read-back: class starts + error
@@ -105,23 +114,39 @@ __global__ void k_prep_shells(int nshell, const int32_t *l, const int32_t *nprim
     }
 }
 
-// class key of each pair: ((la*5 + lb)*8 + Ka-1)*8 + Kb-1; invalid pairs -> NBINS sentinel
-__global__ void k_classify(int64_t n, const int32_t *pairs, int nshell, const int32_t *l, const int32_t *nprim,
-                           int32_t *keys, int32_t *hist, int32_t *err)
+// class key of each pair: ((la*5 + lb)*8 + Ka-1)*8 + Kb-1; invalid pairs -> NBINS
+// sentinel. Counts are aggregated per workgroup in LDS before one global
+// atomic per non-empty bin.
+constexpr int BIN_TPB = 256, BIN_ITEMS = 16;
+
+__global__ __launch_bounds__(BIN_TPB) void k_classify(int64_t n, const int32_t *pairs, int nshell,
+                                                      const int32_t *l, const int32_t *nprim, int32_t *keys,
+                                                      int32_t *hist, int32_t *err)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int a = pairs[2 * i], b = pairs[2 * i + 1];
-    int key = NBINS;
-    if (a < 0 || a >= nshell || b < 0 || b >= nshell) {
-        atomicOr(err, ERR_PAIR_INDEX);
-    } else {
-        int la = l[a], lb = l[b], ka = nprim[a], kb = nprim[b];
-        if (la >= 0 && la <= LMAX && lb >= 0 && lb <= LMAX && ka >= 1 && ka <= KMAX && kb >= 1 && kb <= KMAX)
-            key = ((la * (LMAX + 1) + lb) * 8 + ka - 1) * 8 + kb - 1;
+    __shared__ int32_t lh[NBINS + 1];
+    for (int b = threadIdx.x; b <= NBINS; b += BIN_TPB) lh[b] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * BIN_TPB * BIN_ITEMS;
+    int bad = 0;
+    for (int it = 0; it < BIN_ITEMS; ++it) {
+        int64_t i = base + (int64_t)it * BIN_TPB + threadIdx.x;
+        if (i >= n) break;
+        int a = pairs[2 * i], b = pairs[2 * i + 1];
+        int key = NBINS;
+        if (a < 0 || a >= nshell || b < 0 || b >= nshell) {
+            bad = 1;
+        } else {
+            int la = l[a], lb = l[b], ka = nprim[a], kb = nprim[b];
+            if (la >= 0 && la <= LMAX && lb >= 0 && lb <= LMAX && ka >= 1 && ka <= KMAX && kb >= 1 && kb <= KMAX)
+                key = ((la * (LMAX + 1) + lb) * 8 + ka - 1) * 8 + kb - 1;
+        }
+        keys[i] = key;
+        atomicAdd(&lh[key], 1);
     }
-    keys[i] = key;
-    atomicAdd(&hist[key], 1);
+    if (bad) atomicOr(err, ERR_PAIR_INDEX);
+    __syncthreads();
+    for (int b = threadIdx.x; b <= NBINS; b += BIN_TPB)
+        if (lh[b]) atomicAdd(&hist[b], lh[b]);
 }
 
 // exclusive scan of nb+1 bins by one workgroup of 256 threads; also writes the
@@ -145,12 +170,37 @@ __global__ __launch_bounds__(256) void k_scan_bins(const int32_t *hist, int nb, 
     for (int i = lo; i < hi; ++i) { starts[i] = acc; cursor[i] = acc; acc += hist[i]; }
 }
 
-__global__ void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor, int32_t *order)
+// class-sorted order: each workgroup ranks its items per bin in LDS, reserves
+// one contiguous range per non-empty bin with a single global atomic, then
+// writes the pair ids (order inside a bin is unspecified; results do not
+// depend on it)
+__global__ __launch_bounds__(BIN_TPB) void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor,
+                                                     int32_t *order)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int pos = atomicAdd(&cursor[keys[i]], 1);
-    order[pos] = (int32_t)i;
+    __shared__ int32_t cnt[NBINS + 1];
+    __shared__ int32_t gbase[NBINS + 1];
+    for (int b = threadIdx.x; b <= NBINS; b += BIN_TPB) cnt[b] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * BIN_TPB * BIN_ITEMS;
+    int32_t rank[BIN_ITEMS], key[BIN_ITEMS];
+#pragma unroll
+    for (int it = 0; it < BIN_ITEMS; ++it) {
+        int64_t i = base + (int64_t)it * BIN_TPB + threadIdx.x;
+        key[it] = -1;
+        if (i < n) {
+            key[it] = keys[i];
+            rank[it] = atomicAdd(&cnt[key[it]], 1);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b <= NBINS; b += BIN_TPB)
+        if (cnt[b]) gbase[b] = atomicAdd(&cursor[b], cnt[b]);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < BIN_ITEMS; ++it) {
+        int64_t i = base + (int64_t)it * BIN_TPB + threadIdx.x;
+        if (key[it] >= 0) order[gbase[key[it]] + rank[it]] = (int32_t)i;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -163,7 +213,20 @@ extern "C" int shg_create(shg_ctx **out, void *hip_stream)
     shg_ctx *c = new (std::nothrow) shg_ctx();
     if (!c) return set_err(nullptr, SHG_ENOMEM, "shg_create: out of host memory");
     c->stream = (hipStream_t)hip_stream;
+    for (int la = 0; la <= LMAX; ++la)
+        for (int lb = 0; lb <= LMAX; ++lb)
+            for (int d = 0; d < 2; ++d)
+                for (int op = 0; op < 5; ++op) c->shape[op][la][lb][d] = default_shape(la, lb, d == 1, 64, 48 * 1024);
     hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, c->device);
+        if (e == hipSuccess) {
+            strncpy(c->arch, prop.gcnArchName, sizeof(c->arch) - 1);
+            char *colon = strchr(c->arch, ':');
+            if (colon) *colon = 0;
+        }
+    }
     std::vector<double> tab((size_t)BOYS_NPTS * BOYS_STRIDE);
     build_boys_table(tab.data());
     if (e == hipSuccess) e = hipMalloc((void **)&c->boys, tab.size() * sizeof(double));
@@ -184,12 +247,13 @@ extern "C" void shg_destroy(shg_ctx *c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < NCLASS + 3; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     (void)hipFree(c->boys);
     (void)hipFree(c->w);
     (void)hipFree(c->w2);
     (void)hipFree(c->keys);
     (void)hipFree(c->order);
-    (void)hipFree(c->Obuf);
     (void)hipFree(c->bins);
     (void)hipFree(c->err);
     if (c->host_rb) (void)hipHostFree(c->host_rb);
@@ -249,41 +313,62 @@ static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omeg
 
     if ((rc = grow(c, c->keys, c->keys_cap, (size_t)n))) return rc;
     if ((rc = grow(c, c->order, c->order_cap, (size_t)n))) return rc;
-    if ((rc = grow(c, c->Obuf, c->Obuf_cap, (size_t)n * OSTRIDE))) return rc;
     hipStream_t s = c->stream;
     int32_t *hist = c->bins, *cursor = c->bins + (NBINS_MAX + 1);
+    if (c->prof_on) HIP_TRY(c, hipEventRecord(c->ev[0], s));
     hipLaunchKernelGGL(k_fill_i32, dim3((NBINS + 1 + 255) / 256), dim3(256), 0, s, hist, 0, NBINS + 1);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->err, 0, 1);
     if ((rc = prep_shells(c, sh, LMAX, c->w, c->w_cap))) return rc;
-    unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_classify, dim3(g), dim3(256), 0, s, n, pairs, sh->nshell, sh->l, sh->nprim, c->keys, hist,
-                       c->err);
+    unsigned gb = (unsigned)((n + BIN_TPB * BIN_ITEMS - 1) / (BIN_TPB * BIN_ITEMS));
+    hipLaunchKernelGGL(k_classify, dim3(gb), dim3(BIN_TPB), 0, s, n, pairs, sh->nshell, sh->l, sh->nprim, c->keys,
+                       hist, c->err);
     // the scan leaves the bin starts in `cursor`; they are read back (class
     // starts are every 64th bin) before the scatter advances the cursors
     hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(256), 0, s, hist, NBINS, cursor, cursor);
     HIP_TRY(c, hipMemcpyAsync(c->host_rb, cursor, (NBINS + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(c->host_rb + NBINS + 1, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, n, c->keys, cursor, c->order);
+    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(BIN_TPB), 0, s, n, c->keys, cursor, c->order);
+    if (c->prof_on) HIP_TRY(c, hipEventRecord(c->ev[1], s));
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(s));
     if ((rc = decode_err(c, c->host_rb[NBINS + 1], what))) return rc;
 
-    const contract_fn *ctab[5] = {contract_table_op0(), contract_table_op1(), contract_table_op2(),
-                                  contract_table_op3(), contract_table_op4()};
-    const assemble_fn *atab[5] = {assemble_table_la0(), assemble_table_la1(), assemble_table_la2(),
-                                  assemble_table_la3(), assemble_table_la4()};
+    const tile_fn *ttab[5] = {tile_table_la0(), tile_table_la1(), tile_table_la2(), tile_table_la3(),
+                              tile_table_la4()};
     const int D = deriv ? 1 : 0;
+    TileArgs ta{pairs, c->order, sh->center, sh->nprim, sh->prim_off, sh->exps, c->w, c->boys, out_off, out, dout,
+                omega, (int)op};
+    int prev = NCLASS + 2;   // event before the next class launch
+    int used[NCLASS];
+    int nused = 0;
+    if (c->prof_on) HIP_TRY(c, hipEventRecord(c->ev[NCLASS + 2], s));
     for (int la = 0; la <= LMAX; ++la)
         for (int lb = 0; lb <= LMAX; ++lb) {
             int cls = la * (LMAX + 1) + lb;
             int64_t b0 = c->host_rb[cls * 64], b1 = c->host_rb[(cls + 1) * 64];
             if (b1 <= b0) continue;
-            ContractArgs ca{pairs, c->order, sh->center, sh->nprim, sh->prim_off, sh->exps, c->w, c->boys, omega,
-                            c->Obuf, b0, b1 - b0};
-            ctab[op][(la * 5 + lb) * 2 + D](s, ca);
-            AssembleArgs aa{pairs, c->order, sh->center, out_off, c->Obuf, out, dout, b0, b1 - b0};
-            atab[la][lb * 2 + D](s, aa);
+            ttab[la][lb * 2 + D](s, ta, b0, b1 - b0, c->shape[op][la][lb][D]);
+            if (c->prof_on) {
+                HIP_TRY(c, hipEventRecord(c->ev[2 + cls], s));
+                c->prof_launches[cls][D] += 1;
+                c->prof_pairs[cls][D] += b1 - b0;
+                used[nused++] = cls;
+            }
         }
+    if (c->prof_on) {
+        // per-class kernel time = gap between consecutive events on the stream
+        HIP_TRY(c, hipStreamSynchronize(s));
+        float ms = 0;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        c->prof_bin_ms += ms;
+        c->prof_bin_calls += 1;
+        for (int u = 0; u < nused; ++u) {
+            int cls = used[u];
+            HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[prev], c->ev[2 + cls]));
+            c->prof_ms[cls][D] += ms;
+            prev = 2 + cls;
+        }
+    }
     HIP_TRY(c, hipGetLastError());
     return 0;
 }
@@ -298,6 +383,184 @@ extern "C" int shg_pairs_deriv(shg_ctx *c, const shg_shells *sh, shg_op op, doub
                                int64_t n, const int64_t *out_off, double *out, double *dout)
 {
     return pairs_common(c, sh, op, omega, pairs, n, out_off, out, dout, true);
+}
+
+extern "C" int shg_profile_enable(shg_ctx *c, int on)
+{
+    if (!c) return SHG_EINVAL;
+    if (on && !c->ev[0])
+        for (int i = 0; i < NCLASS + 3; ++i) HIP_TRY(c, hipEventCreate(&c->ev[i]));
+    c->prof_on = on ? 1 : 0;
+    memset(c->prof_ms, 0, sizeof(c->prof_ms));
+    memset(c->prof_launches, 0, sizeof(c->prof_launches));
+    memset(c->prof_pairs, 0, sizeof(c->prof_pairs));
+    c->prof_bin_ms = 0;
+    c->prof_bin_calls = 0;
+    return 0;
+}
+
+extern "C" int shg_profile_read(const shg_ctx *c, int la, int lb, int deriv, double *ms, int64_t *launches,
+                                int64_t *pairs)
+{
+    if (!c || !ms || !launches || !pairs) return SHG_EINVAL;
+    if (la < 0) {   // binning stage (shell preparation, classification, scan, scatter)
+        *ms = c->prof_bin_ms;
+        *launches = c->prof_bin_calls;
+        *pairs = 0;
+        return 0;
+    }
+    if (la > LMAX || lb < 0 || lb > LMAX || (deriv != 0 && deriv != 1)) return SHG_EINVAL;
+    int cls = la * (LMAX + 1) + lb;
+    *ms = c->prof_ms[cls][deriv];
+    *launches = c->prof_launches[cls][deriv];
+    *pairs = c->prof_pairs[cls][deriv];
+    return 0;
+}
+
+static int check_shape(shg_ctx *c, int op, int la, int lb, int deriv, int tp, int rows_pp)
+{
+    if (op < 0 || op > 4 || la < 0 || la > LMAX || lb < 0 || lb > LMAX || (deriv != 0 && deriv != 1))
+        return set_err(c, SHG_EINVAL, "tile shape: class out of range");
+    if (tp != 64 && tp != 128 && tp != 256) return set_err(c, SHG_EINVAL, "tile shape: tp must be 64, 128 or 256");
+    if (rows_pp < 1 || rows_pp > 2 * la + 1) return set_err(c, SHG_EINVAL, "tile shape: rows_pp outside [1, 2la+1]");
+    long bytes = (long)tp * 72 + (long)tp * (deriv ? 4 : 1) * rows_pp * (2 * lb + 1) * 8;
+    if (bytes > 160 * 1024) return set_err(c, SHG_EINVAL, "tile shape: needs %ld bytes of LDS (> 160 KiB)", bytes);
+    return 0;
+}
+
+extern "C" int shg_set_tile_shape(shg_ctx *c, int op, int la, int lb, int deriv, int tp, int rows_pp)
+{
+    if (!c) return SHG_EINVAL;
+    int rc = check_shape(c, op, la, lb, deriv, tp, rows_pp);
+    if (rc) return rc;
+    c->shape[op][la][lb][deriv] = TileShape{tp, rows_pp};
+    return 0;
+}
+
+extern "C" int shg_get_tile_shape(const shg_ctx *c, int op, int la, int lb, int deriv, int *tp, int *rows_pp)
+{
+    if (!c || !tp || !rows_pp || op < 0 || op > 4 || la < 0 || la > LMAX || lb < 0 || lb > LMAX ||
+        (deriv != 0 && deriv != 1))
+        return SHG_EINVAL;
+    *tp = c->shape[op][la][lb][deriv].tp;
+    *rows_pp = c->shape[op][la][lb][deriv].rows_pp;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: times every admissible tile shape of every class present in the
+// caller's pair list and keeps the fastest; the cache file is a small JSON
+// list keyed by (GPU architecture, op, la, lb, deriv)
+// ---------------------------------------------------------------------------
+extern "C" int shg_autotune(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
+                            int64_t n, const int64_t *out_off, double *out, double *dout, int reps)
+{
+    if (!c) return SHG_EINVAL;
+    if (reps < 1) reps = 1;
+    const bool deriv = dout != nullptr;
+    // bin (and evaluate once with the current shapes; this validates the input)
+    int rc = pairs_common(c, sh, op, omega, pairs, n, out_off, out, dout, deriv);
+    if (rc || n == 0) return rc;
+    hipStream_t s = c->stream;
+    const int D = deriv ? 1 : 0;
+    const tile_fn *ttab[5] = {tile_table_la0(), tile_table_la1(), tile_table_la2(), tile_table_la3(),
+                              tile_table_la4()};
+    TileArgs ta{pairs, c->order, sh->center, sh->nprim, sh->prim_off, sh->exps, c->w, c->boys, out_off, out, dout,
+                omega, (int)op};
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    for (int la = 0; la <= LMAX; ++la)
+        for (int lb = 0; lb <= LMAX; ++lb) {
+            int cls = la * (LMAX + 1) + lb;
+            int64_t b0 = c->host_rb[cls * 64], b1 = c->host_rb[(cls + 1) * 64];
+            if (b1 <= b0) continue;
+            float best = 1e30f;
+            TileShape bs = c->shape[op][la][lb][D];
+            const int rows_c[5] = {1, 2, 3, 5, 2 * la + 1};
+            for (int tp = 64; tp <= 256; tp *= 2)
+                for (int r = 0; r < 5; ++r) {
+                    int rows = rows_c[r];
+                    bool dup = false;
+                    for (int q = 0; q < r; ++q) dup |= rows_c[q] == rows;
+                    if (dup || rows > 2 * la + 1) continue;
+                    if (check_shape(c, op, la, lb, D, tp, rows)) continue;
+                    TileShape sh_try{tp, rows};
+                    ttab[la][lb * 2 + D](s, ta, b0, b1 - b0, sh_try);   // warm-up
+                    HIP_TRY(c, hipEventRecord(e0, s));
+                    for (int k = 0; k < reps; ++k) ttab[la][lb * 2 + D](s, ta, b0, b1 - b0, sh_try);
+                    HIP_TRY(c, hipEventRecord(e1, s));
+                    HIP_TRY(c, hipEventSynchronize(e1));
+                    float ms = 0;
+                    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) { best = ms; bs = sh_try; }
+                }
+            c->shape[op][la][lb][D] = bs;
+            c->tune_ms[op][la][lb][D] = best / reps;
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_err(c, 0, "");
+    // leave the caller's buffers holding results of the selected shapes
+    return pairs_common(c, sh, op, omega, pairs, n, out_off, out, dout, deriv);
+}
+
+extern "C" int shg_tuning_save(const shg_ctx *c, const char *path)
+{
+    if (!c || !path) return SHG_EINVAL;
+    FILE *f = fopen(path, "w");
+    if (!f) return SHG_EINVAL;
+    fprintf(f, "{\"arch\": \"%s\", \"shapes\": [\n", c->arch);
+    bool first = true;
+    for (int op = 0; op < 5; ++op)
+        for (int la = 0; la <= LMAX; ++la)
+            for (int lb = 0; lb <= LMAX; ++lb)
+                for (int d = 0; d < 2; ++d) {
+                    if (c->tune_ms[op][la][lb][d] <= 0) continue;
+                    const TileShape &t = c->shape[op][la][lb][d];
+                    fprintf(f, "%s  {\"op\": %d, \"la\": %d, \"lb\": %d, \"deriv\": %d, \"tp\": %d, \"rows_pp\": %d, "
+                               "\"ms\": %.6f}",
+                            first ? "" : ",\n", op, la, lb, d, t.tp, t.rows_pp, c->tune_ms[op][la][lb][d]);
+                    first = false;
+                }
+    fprintf(f, "\n]}\n");
+    fclose(f);
+    return 0;
+}
+
+// Applies the entries of a cache written by shg_tuning_save for this GPU's
+// architecture; malformed or out-of-range entries are skipped (defaults stay).
+// Returns the number of entries applied (>= 0) or SHG_EINVAL if the file
+// cannot be read.
+extern "C" int shg_tuning_load(shg_ctx *c, const char *path)
+{
+    if (!c || !path) return SHG_EINVAL;
+    FILE *f = fopen(path, "r");
+    if (!f) return SHG_EINVAL;
+    std::vector<char> buf;
+    char tmp[4096];
+    size_t k;
+    while ((k = fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + k);
+    fclose(f);
+    buf.push_back(0);
+    const char *txt = buf.data();
+    char arch[64] = {0};
+    const char *pa = strstr(txt, "\"arch\"");
+    if (!pa || sscanf(pa, "\"arch\": \"%63[^\"]\"", arch) != 1 || strcmp(arch, c->arch) != 0) return 0;
+    int applied = 0;
+    for (const char *p = strchr(txt, '{'); p; p = strchr(p + 1, '{')) {
+        int op, la, lb, d, tp, rows;
+        double ms;
+        if (sscanf(p, "{\"op\": %d, \"la\": %d, \"lb\": %d, \"deriv\": %d, \"tp\": %d, \"rows_pp\": %d, \"ms\": %lf}",
+                   &op, &la, &lb, &d, &tp, &rows, &ms) != 7)
+            continue;
+        if (check_shape(c, op, la, lb, d, tp, rows)) continue;
+        c->shape[op][la][lb][d] = TileShape{tp, rows};
+        c->tune_ms[op][la][lb][d] = ms;
+        ++applied;
+    }
+    set_err(c, 0, "");
+    return applied;
 }
 
 extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux, const int32_t *triples, int64_t n,

@@ -1,16 +1,21 @@
-// shg_kernels.h -- HIP kernels of the plain per-class path and their launchers.
+// shg_kernels.h -- HIP kernels of the two-center path and their launchers.
 //
-// Per call the path is:
-//   k_prep_shells    N_l and folded weights per shell          (shell preparation)
-//   k_classify       class key (la, lb, Ka, Kb) per pair, histogram
+// Per call the plain path is:
+//   k_prep_shells    N_l and folded weights per shell                (shell preparation)
+//   k_classify       class key (la, lb, Ka, Kb) per pair, LDS-aggregated histogram
 //   k_scan_bins      exclusive scan of the histogram
 //   k_scatter        class-sorted order of the pairs
-//   k_contract<...>  one thread per shell pair: radial terms of every primitive
-//                    pair (Table S1, Boys by Taylor grid + recurrence) and their
-//                    contraction into O^(k) (eq. O_rab2_deriv), kept in registers
-//   k_assemble<...>  one thread per shell pair and block row (grid.y = row):
-//                    solid harmonics of X = R_a - R_b, Qtilde, block values and
-//                    d/dR_a (eqs. final_r12int_ab, dev_ab, cartesian_dev_x/y/z)
+//   k_tile<la,lb,D>  one launch per class; a workgroup owns a tile of TP shell pairs:
+//     phase 1  G = 256/TP lanes per shell pair evaluate the radial terms of the
+//              primitive pairs (Table S1; Boys by Taylor grid + recurrence) and
+//              contract them into O^(k) (eq. O_rab2_deriv); butterfly reduction
+//              inside the lane group, result in LDS
+//     phase 2  lanes = pairs, waves split the block elements: solid harmonics of
+//              X = R_a - R_b, Qtilde and the element value and d/dR_a
+//              (eqs. final_r12int_ab, dev_ab, cartesian_dev_x/y/z), written to an
+//              LDS tile of `rows_pp` block rows
+//     phase 3  the workgroup copies the LDS tile to the caller's blocks with
+//              consecutive lanes on consecutive doubles (coalesced stores)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,11 +28,9 @@ constexpr int LMAX = 4;        // two-center / orbital shells
 constexpr int KMAX = 7;
 constexpr int NCLASS = (LMAX + 1) * (LMAX + 1);
 constexpr int NBINS = NCLASS * 64;      // (la, lb, Ka-1, Kb-1)
-constexpr int OSTRIDE = 8;              // doubles per pair in the O^(k) scratch buffer
-constexpr int CONTRACT_TPB = 128;
-constexpr int ASSEMBLE_TPB = 64;
+constexpr int TILE_THREADS = 256;
 
-struct ContractArgs {
+struct TileArgs {
     const int32_t *pairs;      // [n][2]
     const int32_t *order;      // class-sorted pair ids
     const double *center;      // [nshell][3]
@@ -36,94 +39,197 @@ struct ContractArgs {
     const double *exps;
     const double *w;           // folded weights N_l c / (2 alpha)^l
     const double *tab;         // Boys grid
-    double omega;
-    double *Obuf;              // [sorted position][OSTRIDE]
-    int64_t start, count;
-};
-
-struct AssembleArgs {
-    const int32_t *pairs;
-    const int32_t *order;
-    const double *center;
     const int64_t *out_off;
-    const double *Obuf;
     double *out, *dout;
-    int64_t start, count;
+    double omega;
+    int op;
 };
 
-template <int LA, int LB, int OP, bool D>
-__global__ __launch_bounds__(CONTRACT_TPB) void k_contract(ContractArgs a)
+// tile shape: TP pairs (64, 128 or 256) and rows_pp block rows per LDS pass
+struct TileShape {
+    int tp, rows_pp;
+};
+
+template <int KLO, int KHI>
+__device__ __forceinline__ void radial_rt(int op, double a, double b, double R2, double omega,
+                                          const double *__restrict__ tab, double (&g)[KHI - KLO + 1])
 {
-    int64_t t = (int64_t)blockIdx.x * CONTRACT_TPB + threadIdx.x;
-    if (t >= a.count) return;
-    int64_t pos = a.start + t;
-    int p = a.order[pos];
-    int sa = a.pairs[2 * (int64_t)p], sb = a.pairs[2 * (int64_t)p + 1];
-    double X0 = a.center[3 * sa] - a.center[3 * sb];
-    double X1 = a.center[3 * sa + 1] - a.center[3 * sb + 1];
-    double X2 = a.center[3 * sa + 2] - a.center[3 * sb + 2];
-    double R2 = X0 * X0 + X1 * X1 + X2 * X2;
-    int64_t oa = a.prim_off[sa], ob = a.prim_off[sb];
-    double O[PairK<LA, LB, D>::NK];
-    contract_pair<LA, LB, OP, D>(a.exps + oa, a.w + oa, a.nprim[sa], a.exps + ob, a.w + ob, a.nprim[sb], R2,
-                                 a.omega, a.tab, O);
+    switch (op) {
+    case OP_OVERLAP: radial<OP_OVERLAP, KLO, KHI>(a, b, R2, omega, tab, g); break;
+    case OP_COULOMB: radial<OP_COULOMB, KLO, KHI>(a, b, R2, omega, tab, g); break;
+    case OP_ERF: radial<OP_ERF, KLO, KHI>(a, b, R2, omega, tab, g); break;
+    case OP_ERFC: radial<OP_ERFC, KLO, KHI>(a, b, R2, omega, tab, g); break;
+    default: radial<OP_GAUSS, KLO, KHI>(a, b, R2, omega, tab, g); break;
+    }
+}
+
+// Makes the harmonics table, the contracted radial terms and X opaque to the
+// optimiser: placed between block elements it stops values of one element from
+// being shared with (and kept live for) the next, which bounds the register
+// footprint of the large classes at the cost of recomputing a few W entries.
+template <int L, int NK>
+__device__ __forceinline__ void reg_fence(RTab<L> &R, double (&O)[NK], double (&X)[3])
+{
 #pragma unroll
-    for (int k = 0; k < PairK<LA, LB, D>::NK; ++k) a.Obuf[pos * OSTRIDE + k] = O[k];
+    for (int k = 0; k < (L + 1) * (L + 2) / 2; ++k) asm volatile("" : "+v"(R.c[k]), "+v"(R.s[k]));
+#pragma unroll
+    for (int k = 0; k < NK; ++k) asm volatile("" : "+v"(O[k]));
+    asm volatile("" : "+v"(X[0]), "+v"(X[1]), "+v"(X[2]));
 }
 
 template <int LA, int LB, bool D>
-__global__ __launch_bounds__(ASSEMBLE_TPB) void k_assemble(AssembleArgs a)
+constexpr int tile_smem_bytes(int tp, int rows_pp)
 {
-    int64_t t = (int64_t)blockIdx.x * ASSEMBLE_TPB + threadIdx.x;
-    if (t >= a.count) return;
-    int64_t pos = a.start + t;
-    int p = a.order[pos];
-    int sa = a.pairs[2 * (int64_t)p], sb = a.pairs[2 * (int64_t)p + 1];
-    double X[3] = {a.center[3 * sa] - a.center[3 * sb], a.center[3 * sa + 1] - a.center[3 * sb + 1],
-                   a.center[3 * sa + 2] - a.center[3 * sb + 2]};
-    double O[PairK<LA, LB, D>::NK];
+    return tp * 8 * 8 + tp * 8 + tp * (D ? 4 : 1) * rows_pp * (2 * LB + 1) * 8;
+}
+
+// One tile of `tcount` (<= shape.tp) class-(LA,LB) pairs starting at sorted
+// position `tstart`. smem: dynamic LDS of tile_smem_bytes(tp, rows_pp).
+template <int LA, int LB, bool D>
+__device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, int tcount, TileShape shape,
+                                           char *smem)
+{
+    using PK = PairK<LA, LB, D>;
+    constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, SZ = NA * NB, NC = D ? 4 : 1;
+    const int TP = shape.tp, rows_pp = shape.rows_pp;
+    double *sO = (double *)smem;                 // [TP][8]
+    int64_t *sOff = (int64_t *)(sO + TP * 8);    // [TP]
+    double *sT = (double *)(sOff + TP);          // [TP][NC][rows_pp * NB]
+    const int tid = threadIdx.x;
+
+    // ---- phase 1: radial terms and contraction, G lanes per shell pair ----
+    {
+        const int G = TILE_THREADS / TP;
+        const int i = tid / G, g = tid - (tid / G) * G;
+        const bool live = i < tcount;
+        const int p = a.order[tstart + (live ? i : 0)];
+        const int sa = a.pairs[2 * (int64_t)p], sb = a.pairs[2 * (int64_t)p + 1];
+        const double X0 = a.center[3 * sa] - a.center[3 * sb];
+        const double X1 = a.center[3 * sa + 1] - a.center[3 * sb + 1];
+        const double X2 = a.center[3 * sa + 2] - a.center[3 * sb + 2];
+        const double R2 = X0 * X0 + X1 * X1 + X2 * X2;
+        const int64_t oa = a.prim_off[sa], ob = a.prim_off[sb];
+        const int kb = a.nprim[sb];
+        const int P = live ? a.nprim[sa] * kb : 0;
+        double O[PK::NK];
 #pragma unroll
-    for (int k = 0; k < PairK<LA, LB, D>::NK; ++k) O[k] = a.Obuf[pos * OSTRIDE + k];
+        for (int k = 0; k < PK::NK; ++k) O[k] = 0.0;
+        for (int q = g; q < P; q += G) {
+            const int ia = q / kb, ib = q - ia * kb;
+            double gk[PK::NK];
+            radial_rt<PK::KLO, PK::KHI>(a.op, a.exps[oa + ia], a.exps[ob + ib], R2, a.omega, a.tab, gk);
+            const double ww = a.w[oa + ia] * a.w[ob + ib];
+#pragma unroll
+            for (int k = 0; k < PK::NK; ++k) O[k] = fma(ww, gk[k], O[k]);
+        }
+        for (int m = 1; m < G; m <<= 1)
+#pragma unroll
+            for (int k = 0; k < PK::NK; ++k) O[k] += __shfl_xor(O[k], m, G);
+        if (live && g == 0) {
+#pragma unroll
+            for (int k = 0; k < PK::NK; ++k) sO[i * 8 + k] = O[k];
+            sOff[i] = a.out_off[p];
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 2: angular part; lanes = pairs, waves split the elements ----
+    const int lane = tid & 63, wave = tid >> 6;
+    const int PW = TP / 64, EW = (TILE_THREADS / 64) / PW;
+    const int pg = wave % PW, es = wave / PW;
+    const int i = pg * 64 + lane;
+    const bool live = i < tcount;
+    double X[3], O[PK::NK];
+    {
+        const int p = a.order[tstart + (live ? i : 0)];
+        const int sa = a.pairs[2 * (int64_t)p], sb = a.pairs[2 * (int64_t)p + 1];
+        X[0] = a.center[3 * sa] - a.center[3 * sb];
+        X[1] = a.center[3 * sa + 1] - a.center[3 * sb + 1];
+        X[2] = a.center[3 * sa + 2] - a.center[3 * sb + 2];
+#pragma unroll
+        for (int k = 0; k < PK::NK; ++k) O[k] = live ? sO[i * 8 + k] : 0.0;
+    }
     RTab<cmax(LA, LB)> R;
     solid_R<cmax(LA, LB)>(X[0], X[1], X[2], R);
-    constexpr int NB = 2 * LB + 1, SZ = (2 * LA + 1) * NB;
-    int64_t off = a.out_off[p];
-    const int row = blockIdx.y;   // uniform across the wave
-    static_for<0, 2 * LA + 1>([&](auto IAA) {
-        constexpr int IA = decltype(IAA)::value;
-        if (row == IA)
-            pair_row<LA, LB, IA, D>(R, O, X, a.out + off + IA * NB, D ? a.dout + 3 * off + IA * NB : nullptr, SZ);
-    });
-}
 
-typedef void (*contract_fn)(hipStream_t, const ContractArgs &);
-typedef void (*assemble_fn)(hipStream_t, const AssembleArgs &);
-
-template <int LA, int LB, int OP, bool D>
-void launch_contract(hipStream_t s, const ContractArgs &a)
-{
-    unsigned g = (unsigned)((a.count + CONTRACT_TPB - 1) / CONTRACT_TPB);
-    hipLaunchKernelGGL((k_contract<LA, LB, OP, D>), dim3(g), dim3(CONTRACT_TPB), 0, s, a);
+    for (int r0 = 0; r0 < NA; r0 += rows_pp) {
+        const int r1 = min(NA, r0 + rows_pp);
+        const int SEG = (r1 - r0) * NB;
+        static_for<0, SZ>([&](auto EE) {
+            constexpr int E = decltype(EE)::value;
+            constexpr int IA = E / NB, IB = E % NB;
+            if (IA >= r0 && IA < r1 && ((E - r0 * NB) % EW) == es) {
+                reg_fence(R, O, X);
+                double res[NC];
+                pair_elem<LA, LB, IA, IB, D>(R, O, X, res);
+                if (live) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) sT[(i * NC + c) * SEG + (E - r0 * NB)] = res[c];
+                }
+            }
+        });
+        __syncthreads();
+        // ---- phase 3: coalesced copy of the LDS tile into the blocks ----
+        const int per = NC * SEG;
+        const int total = tcount * per;
+        for (int f = tid; f < total; f += TILE_THREADS) {
+            const int ii = f / per, rem = f - ii * per;
+            const int c = rem / SEG, s = rem - c * SEG;
+            const int64_t off = sOff[ii];
+            const double v = sT[f];
+            if (c == 0)
+                a.out[off + r0 * NB + s] = v;
+            else
+                a.dout[3 * off + (c - 1) * SZ + r0 * NB + s] = v;
+        }
+        __syncthreads();
+    }
 }
 
 template <int LA, int LB, bool D>
-void launch_assemble(hipStream_t s, const AssembleArgs &a)
+__global__ __launch_bounds__(TILE_THREADS) void k_tile(TileArgs a, int64_t start, int64_t count, TileShape shape)
 {
-    unsigned g = (unsigned)((a.count + ASSEMBLE_TPB - 1) / ASSEMBLE_TPB);
-    hipLaunchKernelGGL((k_assemble<LA, LB, D>), dim3(g, 2 * LA + 1), dim3(ASSEMBLE_TPB), 0, s, a);
+    extern __shared__ __align__(16) char smem[];
+    const int64_t tstart = start + (int64_t)blockIdx.x * shape.tp;
+    const int tcount = (int)min((int64_t)shape.tp, start + count - tstart);
+    tile_pairs<LA, LB, D>(a, tstart, tcount, shape, smem);
 }
 
-// dispatch tables, defined in the per-operator / per-l_a translation units:
-// contract_table(op)[(la * 5 + lb) * 2 + D], assemble_table(la)[lb * 2 + D]
-const contract_fn *contract_table_op0();
-const contract_fn *contract_table_op1();
-const contract_fn *contract_table_op2();
-const contract_fn *contract_table_op3();
-const contract_fn *contract_table_op4();
-const assemble_fn *assemble_table_la0();
-const assemble_fn *assemble_table_la1();
-const assemble_fn *assemble_table_la2();
-const assemble_fn *assemble_table_la3();
-const assemble_fn *assemble_table_la4();
+typedef void (*tile_fn)(hipStream_t, const TileArgs &, int64_t start, int64_t count, TileShape shape);
+
+template <int LA, int LB, bool D>
+void launch_tile(hipStream_t s, const TileArgs &a, int64_t start, int64_t count, TileShape shape)
+{
+    unsigned g = (unsigned)((count + shape.tp - 1) / shape.tp);
+    size_t smem = (size_t)tile_smem_bytes<LA, LB, D>(shape.tp, shape.rows_pp);
+    static bool attr_set = false;   // allow up to the full 160 KiB of LDS per workgroup
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_tile<LA, LB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_tile<LA, LB, D>), dim3(g), dim3(TILE_THREADS), smem, s, a, start, count, shape);
+}
+
+// default tile shape of class (la, lb, D) under an LDS budget (bytes)
+inline TileShape default_shape(int la, int lb, bool D, int tp, int lds_budget)
+{
+    int NA = 2 * la + 1, NB = 2 * lb + 1, NC = D ? 4 : 1;
+    int fixed = tp * 8 * 8 + tp * 8;
+    int per_row = tp * NC * NB * 8;
+    int rows = (lds_budget - fixed) / per_row;
+    if (rows < 1) rows = 1;
+    if (rows > NA) rows = NA;
+    int passes = (NA + rows - 1) / rows;
+    rows = (NA + passes - 1) / passes;
+    return TileShape{tp, rows};
+}
+
+// dispatch tables (one translation unit per l_a): tile_table_la<l_a>()[lb * 2 + D]
+const tile_fn *tile_table_la0();
+const tile_fn *tile_table_la1();
+const tile_fn *tile_table_la2();
+const tile_fn *tile_table_la3();
+const tile_fn *tile_table_la4();
 
 }  // namespace shg

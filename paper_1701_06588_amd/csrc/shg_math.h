@@ -392,64 +392,60 @@ SHG_HD SHG_INL void contract_pair(const double *__restrict__ ea, const double *_
 }
 
 // ---------------------------------------------------------------------------
-// One block row (fixed m_a = IA - LA) of (a|O|b) and, with D, of d/dR_a:
+// One block element (m_a = IA - LA, m_b = IB - LB) of (a|O|b) and, with D, of
+// d/dR_a:
 //   value  = A_a A_b sum_j O^(la+lb-j) Qhat_j                    eq. final_r12int_ab
 //   d/dR_i = A_a A_b [ 2 X_i sum_j O^(la+lb-j+1) Qhat_j
 //                      + sum_j O^(la+lb-j) dQhat_j/dR_i ]          eq. dev_ab
 // with dQtilde/dR_i from (l-1) terms, eqs. cartesian_dev_x/y/z (with the
 // factor A_a A_b taken out, the ratios of A's there reduce to 1).
-// out_row / dout_row point at element (IA, 0) of the block; dstride = SZ.
+// res[0] = value; with D res[1..3] = d/dR_a,{x,y,z}.
 // ---------------------------------------------------------------------------
-template <int LA, int LB, int IA, bool D, int L>
-SHG_HD SHG_INL void pair_row(const RTab<L> &R, const double *O, const double X[3],
-                             double *__restrict__ out_row, double *__restrict__ dout_row, int dstride)
+template <int LA, int LB, int IA, int IB, bool D, int L>
+SHG_HD SHG_INL void pair_elem(const RTab<L> &R, const double *O, const double X[3], double *res)
 {
     using PK = PairK<LA, LB, D>;
-    constexpr int JM = cmin(LA, LB), NB = 2 * LB + 1;
+    constexpr int JM = cmin(LA, LB);
     constexpr int MA = IA - LA, MUA = cabs(MA), TA = MA < 0 ? 1 : 0;
-    constexpr double SA = TA ? -1.0 : 1.0;
-    static_for<0, NB>([&](auto IBB) {
-        constexpr int IB = decltype(IBB)::value;
-        constexpr int MB = IB - LB, MUB = cabs(MB), TB = MB < 0 ? 1 : 0;
-        constexpr double SB = TB ? -1.0 : 1.0;
-        constexpr double AA = A_lm(LA, MUA) * A_lm(LB, MUB);
-        double v = 0.0, v1 = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
-        static_for<0, JM + 1>([&](auto JJ) {
-            constexpr int J = decltype(JJ)::value;
-            constexpr int K0 = LA + LB - J - PK::KLO;
-            if constexpr (qhat_nz(LA, MUA, TA, LB, MUB, TB, J)) {
-                double q = qhat<LA, MUA, TA, LB, MUB, TB, J>(R);
-                v = fma(O[K0], q, v);
-                if constexpr (D) v1 = fma(O[K0 + 1], q, v1);
-            }
-            if constexpr (D) {
-                double tx = 0.0, ty = 0.0, tz = 0.0;
-                qhat_acc<LA - 1, MUA + 1, TA, LB, MUB, TB, J>(R, 1.0, tx);
-                qhat_acc<LA - 1, MUA - 1, TA, LB, MUB, TB, J>(R, -1.0, tx);
-                qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, TB, J>(R, -1.0, tx);
-                qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, TB, J>(R, 1.0, tx);
-                qhat_acc<LA - 1, MUA + 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
-                qhat_acc<LA - 1, MUA - 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
-                qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, 1 - TB, J>(R, -SB, ty);
-                qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, 1 - TB, J>(R, -SB, ty);
-                qhat_acc<LA - 1, MUA, TA, LB, MUB, TB, J>(R, 2.0, tz);
-                qhat_acc<LA, MUA, TA, LB - 1, MUB, TB, J>(R, -2.0, tz);
-                dx = fma(O[K0], tx, dx);
-                dy = fma(O[K0], ty, dy);
-                dz = fma(O[K0], tz, dz);
-            }
-        });
-        out_row[IB] = AA * v;
+    constexpr int MB = IB - LB, MUB = cabs(MB), TB = MB < 0 ? 1 : 0;
+    constexpr double SA = TA ? -1.0 : 1.0, SB = TB ? -1.0 : 1.0;
+    constexpr double AA = A_lm(LA, MUA) * A_lm(LB, MUB);
+    double v = 0.0, v1 = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
+    static_for<0, JM + 1>([&](auto JJ) {
+        constexpr int J = decltype(JJ)::value;
+        constexpr int K0 = LA + LB - J - PK::KLO;
+        if constexpr (qhat_nz(LA, MUA, TA, LB, MUB, TB, J)) {
+            double q = qhat<LA, MUA, TA, LB, MUB, TB, J>(R);
+            v = fma(O[K0], q, v);
+            if constexpr (D) v1 = fma(O[K0 + 1], q, v1);
+        }
         if constexpr (D) {
-            double t1 = 2.0 * v1;
-            dout_row[IB] = AA * fma(t1, X[0], dx);
-            dout_row[dstride + IB] = AA * fma(t1, X[1], dy);
-            dout_row[2 * dstride + IB] = AA * fma(t1, X[2], dz);
+            double tx = 0.0, ty = 0.0, tz = 0.0;
+            qhat_acc<LA - 1, MUA + 1, TA, LB, MUB, TB, J>(R, 1.0, tx);
+            qhat_acc<LA - 1, MUA - 1, TA, LB, MUB, TB, J>(R, -1.0, tx);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, TB, J>(R, -1.0, tx);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, TB, J>(R, 1.0, tx);
+            qhat_acc<LA - 1, MUA + 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
+            qhat_acc<LA - 1, MUA - 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, 1 - TB, J>(R, -SB, ty);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, 1 - TB, J>(R, -SB, ty);
+            qhat_acc<LA - 1, MUA, TA, LB, MUB, TB, J>(R, 2.0, tz);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB, TB, J>(R, -2.0, tz);
+            dx = fma(O[K0], tx, dx);
+            dy = fma(O[K0], ty, dy);
+            dz = fma(O[K0], tz, dz);
         }
     });
+    res[0] = AA * v;
+    if constexpr (D) {
+        double t1 = 2.0 * v1;
+        res[1] = AA * fma(t1, X[0], dx);
+        res[2] = AA * fma(t1, X[1], dy);
+        res[3] = AA * fma(t1, X[2], dz);
+    }
 }
 
-// whole block (host-side use and small classes): all rows
+// whole block (host-side use): every element
 template <int LA, int LB, bool D>
 SHG_HD SHG_INL void pair_block_from_O(const double *O, const double X[3], double *__restrict__ out,
                                       double *__restrict__ dout)
@@ -457,9 +453,16 @@ SHG_HD SHG_INL void pair_block_from_O(const double *O, const double X[3], double
     constexpr int NB = 2 * LB + 1, SZ = (2 * LA + 1) * NB;
     RTab<cmax(LA, LB)> R;
     solid_R<cmax(LA, LB)>(X[0], X[1], X[2], R);
-    static_for<0, 2 * LA + 1>([&](auto IAA) {
-        constexpr int IA = decltype(IAA)::value;
-        pair_row<LA, LB, IA, D>(R, O, X, out + IA * NB, D ? dout + IA * NB : nullptr, SZ);
+    static_for<0, SZ>([&](auto EE) {
+        constexpr int E = decltype(EE)::value;
+        double res[D ? 4 : 1];
+        pair_elem<LA, LB, E / NB, E % NB, D>(R, O, X, res);
+        out[E] = res[0];
+        if constexpr (D) {
+            dout[E] = res[1];
+            dout[SZ + E] = res[2];
+            dout[2 * SZ + E] = res[3];
+        }
     });
 }
 

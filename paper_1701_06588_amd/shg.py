@@ -16,7 +16,9 @@ LIB_PATH = os.path.join(HERE, "libshg.so")
 
 OPS = {"overlap": 0, "coulomb": 1, "erf": 2, "erfc": 3, "gauss": 4}
 ERRORS = {-1: "SHG_EINVAL", -2: "SHG_ENOMEM", -3: "SHG_EDEVICE"}
-EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pairs_deriv", "shg_aab")
+EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pairs_deriv", "shg_aab",
+           "shg_set_tile_shape", "shg_get_tile_shape", "shg_autotune", "shg_tuning_save", "shg_tuning_load",
+           "shg_profile_enable", "shg_profile_read")
 
 
 class ShgShells(C.Structure):
@@ -55,6 +57,15 @@ def load_library(path: str = LIB_PATH):
     lib.shg_pairs_deriv.restype = C.c_int
     lib.shg_aab.argtypes = [P, C.POINTER(ShgShells), C.POINTER(ShgShells), P, C.c_int64, P, P, P]
     lib.shg_aab.restype = C.c_int
+    I = C.c_int
+    lib.shg_set_tile_shape.argtypes = [P, I, I, I, I, I, I]
+    lib.shg_get_tile_shape.argtypes = [P, I, I, I, I, C.POINTER(I), C.POINTER(I)]
+    lib.shg_autotune.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, P, P, P, I]
+    lib.shg_tuning_save.argtypes = [P, C.c_char_p]
+    lib.shg_tuning_load.argtypes = [P, C.c_char_p]
+    lib.shg_profile_enable.argtypes = [P, I]
+    lib.shg_profile_read.argtypes = [P, I, I, I, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]
     _lib = lib
     return lib
 
@@ -109,6 +120,38 @@ class Engine:
     def _check(self, rc):
         if rc != 0:
             raise ShgError(rc, self.lib.shg_last_error(self.ctx).decode())
+
+    def set_tile_shape(self, op, la, lb, deriv, tp, rows_pp):
+        self._check(self.lib.shg_set_tile_shape(self.ctx, OPS[op], la, lb, int(deriv), tp, rows_pp))
+
+    def get_tile_shape(self, op, la, lb, deriv):
+        tp, rows = C.c_int(), C.c_int()
+        self._check(self.lib.shg_get_tile_shape(self.ctx, OPS[op], la, lb, int(deriv), C.byref(tp),
+                                                C.byref(rows)))
+        return tp.value, rows.value
+
+    def autotune(self, dsh, op, omega, pairs, out_off, out, dout=None, reps=3):
+        self._check(self.lib.shg_autotune(self.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs),
+                                          int(pairs.shape[0]), _ptr(out_off), _ptr(out), _ptr(dout), reps))
+
+    def tuning_save(self, path):
+        self._check(self.lib.shg_tuning_save(self.ctx, path.encode()))
+
+    def tuning_load(self, path) -> int:
+        rc = self.lib.shg_tuning_load(self.ctx, path.encode())
+        if rc < 0:
+            self._check(rc)
+        return rc
+
+    def profile_enable(self, on=True):
+        self._check(self.lib.shg_profile_enable(self.ctx, int(on)))
+
+    def profile_read(self, la, lb, deriv):
+        """(ms, launches, pairs) accumulated for class (la, lb, deriv); la < 0: binning."""
+        ms, nl, npairs = C.c_double(), C.c_int64(), C.c_int64()
+        self._check(self.lib.shg_profile_read(self.ctx, la, lb, int(deriv), C.byref(ms), C.byref(nl),
+                                              C.byref(npairs)))
+        return ms.value, nl.value, npairs.value
 
     def shells(self, sh) -> DeviceShells:
         return DeviceShells(sh, self.torch.device("cuda", self.torch.cuda.current_device()))
