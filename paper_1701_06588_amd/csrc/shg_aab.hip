@@ -1,0 +1,313 @@
+// shg_aab.hip -- three-index overlap (a b a~) (Sec. II.D) and its d/dR_A.
+//
+// Per call:
+//   k_prep_shells     weights of the orbital and auxiliary shell tables
+//   k_aab_classify    class key (la, la~, lb) per triple + validation; LDS histogram
+//   k_scan_bins / k_scatter (shared with the two-center path)
+//   per class, in chunks of at most AAB_CHUNK triples:
+//     k_aab_radial    G lanes per triple: P^(k)_{La} for every La of the class from
+//                     the primitive triples (eqs. Pa_aba, devsra2ms)
+//     k_tile<La,lb,D> (three-index mode) the two-center blocks Y_La = (La Ma | lb mb)
+//                     with P_La as contracted monopole (eq. final (a b a~) formula),
+//                     into scratch
+//     k_aab_gaunt     out[ma][ma~][mb] = sum_{La,Ma} G^{La,la,la~}_{Ma,ma,ma~} Y_La[Ma][mb]
+//                     (real Gaunt coefficients, eq. CG_expansion), coalesced stores
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <utility>
+#include <vector>
+
+#include "gaunt_table.h"
+#include "shg_ctx.h"
+
+using namespace shg;
+
+namespace {
+
+constexpr int AAB_LA = 3, AAB_LT = 6, AAB_LB = 3;
+constexpr int AAB_NCLASS = (AAB_LA + 1) * (AAB_LT + 1) * (AAB_LB + 1);
+constexpr int AAB_PSTRIDE = 32;
+constexpr int64_t AAB_CHUNK = 1 << 17;
+constexpr int RAD_G = 8, RAD_TPB = 256;
+
+__device__ __forceinline__ int aab_key(int la, int lt, int lb) { return (la * (AAB_LT + 1) + lt) * (AAB_LB + 1) + lb; }
+
+__global__ __launch_bounds__(256) void k_aab_classify(int64_t n, const int32_t *tri, int norb, const double *oc,
+                                                      const int32_t *ol, int naux, const double *xc,
+                                                      const int32_t *xl, int32_t *keys, int32_t *hist, int32_t *err)
+{
+    __shared__ int32_t lh[AAB_NCLASS + 1];
+    for (int b = threadIdx.x; b <= AAB_NCLASS; b += 256) lh[b] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * 256 * 16;
+    int bad = 0;
+    for (int it = 0; it < 16; ++it) {
+        int64_t i = base + (int64_t)it * 256 + threadIdx.x;
+        if (i >= n) break;
+        int a = tri[3 * i], t = tri[3 * i + 1], b = tri[3 * i + 2];
+        int key = AAB_NCLASS;
+        if (a < 0 || a >= norb || t < 0 || t >= naux || b < 0 || b >= norb) {
+            bad |= ERR_PAIR_INDEX;
+        } else if (oc[3 * a] != xc[3 * t] || oc[3 * a + 1] != xc[3 * t + 1] || oc[3 * a + 2] != xc[3 * t + 2]) {
+            bad |= ERR_AAB_CENTER;
+        } else {
+            int la = ol[a], lt = xl[t], lb = ol[b];
+            if (la < 0 || la > AAB_LA || lt < 0 || lt > AAB_LT || lb < 0 || lb > AAB_LB)
+                bad |= ERR_AAB_L;
+            else
+                key = aab_key(la, lt, lb);
+        }
+        keys[i] = key;
+        atomicAdd(&lh[key], 1);
+    }
+    if (bad) atomicOr(err, bad);
+    __syncthreads();
+    for (int b = threadIdx.x; b <= AAB_NCLASS; b += 256)
+        if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
+struct AabRadArgs {
+    const int32_t *tri, *order;
+    const double *oc;
+    const int32_t *onp;
+    const int64_t *ooff;
+    const double *oexp, *ow;     // orbital exponents and weights N c / (2 alpha)^l
+    const int32_t *xnp;
+    const int64_t *xoff;
+    const double *xexp, *xw;     // auxiliary exponents and weights
+    double *P;                   // [pos - pbase][AAB_PSTRIDE]
+    int64_t pbase, start, count;
+};
+
+// G lanes per triple; lane g takes primitive triples q = g, g+G, ...; xor butterfly
+template <int LA, int LT, int LB, bool D>
+__global__ __launch_bounds__(RAD_TPB) void k_aab_radial(AabRadArgs a)
+{
+    using AK = AabK<LA, LT, LB, D>;
+    const int64_t t = (int64_t)blockIdx.x * RAD_TPB + threadIdx.x;
+    const int64_t slot = t / RAD_G;
+    const int g = (int)(t % RAD_G);
+    const bool live = slot < a.count;
+    const int64_t pos = a.start + (live ? slot : 0);
+    const int p = a.order[pos];
+    const int sa = a.tri[3 * (int64_t)p], st = a.tri[3 * (int64_t)p + 1], sb = a.tri[3 * (int64_t)p + 2];
+    const double X0 = a.oc[3 * sa] - a.oc[3 * sb], X1 = a.oc[3 * sa + 1] - a.oc[3 * sb + 1],
+                 X2 = a.oc[3 * sa + 2] - a.oc[3 * sb + 2];
+    const double R2 = X0 * X0 + X1 * X1 + X2 * X2;
+    const int ka = a.onp[sa], kt = a.xnp[st], kb = a.onp[sb];
+    const int64_t oa = a.ooff[sa], ot = a.xoff[st], ob = a.ooff[sb];
+    const int NP = live ? ka * kt * kb : 0;
+    double P[AK::NLA][8];
+#pragma unroll
+    for (int i = 0; i < AK::NLA; ++i)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) P[i][k] = 0.0;
+    for (int q = g; q < NP; q += RAD_G) {
+        const int ib = q % kb, r = q / kb, it = r % kt, ia = r / kt;
+        const double al = a.oexp[oa + ia], at = a.xexp[ot + it], be = a.oexp[ob + ib];
+        // the a and a~ weights without their (2 alpha)^l factors
+        double fa = a.ow[oa + ia], ft = a.xw[ot + it];
+#pragma unroll
+        for (int k = 0; k < LA; ++k) fa *= 2.0 * al;
+#pragma unroll
+        for (int k = 0; k < LT; ++k) ft *= 2.0 * at;
+        aab_accumulate<LA, LT, LB, D>(al + at, be, R2, fa * ft * a.ow[ob + ib], P);
+    }
+#pragma unroll
+    for (int m = 1; m < RAD_G; m <<= 1)
+#pragma unroll
+        for (int i = 0; i < AK::NLA; ++i)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) P[i][k] += __shfl_xor(P[i][k], m, RAD_G);
+    if (live && g == 0) {
+        double *dst = a.P + (pos - a.pbase) * AAB_PSTRIDE;
+#pragma unroll
+        for (int i = 0; i < AK::NLA; ++i)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dst[i * 8 + k] = P[i][k];
+    }
+}
+
+typedef void (*aab_rad_fn)(hipStream_t, const AabRadArgs &);
+
+template <int LA, int LT, int LB, bool D>
+void launch_aab_radial(hipStream_t s, const AabRadArgs &a)
+{
+    unsigned g = (unsigned)((a.count * RAD_G + RAD_TPB - 1) / RAD_TPB);
+    hipLaunchKernelGGL((k_aab_radial<LA, LT, LB, D>), dim3(g), dim3(RAD_TPB), 0, s, a);
+}
+
+template <int... I>
+const aab_rad_fn *make_rad_table(std::integer_sequence<int, I...>)
+{
+    // index ((la * 7 + lt) * 4 + lb) * 2 + D
+    static const aab_rad_fn t[] = {&launch_aab_radial<I / 56, (I / 8) % 7, (I / 2) % 4, (I % 2) == 1>...};
+    return t;
+}
+
+const aab_rad_fn *rad_table()
+{
+    static const aab_rad_fn *t = make_rad_table(std::make_integer_sequence<int, AAB_NCLASS * 2>{});
+    return t;
+}
+
+struct GauntArgs {
+    const int32_t *order;
+    const int64_t *out_off;
+    const int32_t *gidx;    // {start, count} per (ma, mt) of the class's (la, lt)
+    const int32_t *glm;     // {L, M}
+    const double *gg;
+    const double *Yv, *Yd;
+    double *out, *dout;
+    int64_t start, count, ys;
+    int la, lt, lb, nc, lamin;
+};
+
+// one output double per thread: (triple, component, ma, mt, mb) flattened so that
+// consecutive threads write consecutive elements of the same block
+__global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
+{
+    const int NT = 2 * a.lt + 1, NB = 2 * a.lb + 1, SZ = (2 * a.la + 1) * NT * NB;
+    const int64_t per = (int64_t)a.nc * SZ;
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (f >= a.count * per) return;
+    const int64_t q = f / per;
+    const int e = (int)(f - q * per);
+    const int c = e / SZ, rem = e - c * SZ;
+    const int mb = rem % NB, r2 = rem / NB, mt = r2 % NT, ma = r2 / NT;
+    const int2 se = ((const int2 *)a.gidx)[ma * NT + mt];
+    const int64_t ybase = q * a.ys;
+    double v = 0.0;
+    for (int k = se.x; k < se.x + se.y; ++k) {
+        const int L = a.glm[2 * k], M = a.glm[2 * k + 1];
+        const int nL = (L - a.lamin) / 2;
+        const int64_t loff = (int64_t)NB * (nL * (2 * a.lamin + 1) + 2 * nL * (nL - 1));   // sum of (2L'+1) NB, L' < L
+        const int row = (M + L) * NB + mb;
+        const double y = (c == 0) ? a.Yv[ybase + loff + row]
+                                  : a.Yd[3 * (ybase + loff) + (int64_t)(c - 1) * (2 * L + 1) * NB + row];
+        v = fma(a.gg[k], y, v);
+    }
+    const int64_t off = a.out_off[a.order[a.start + q]];
+    if (c == 0)
+        a.out[off + rem] = v;
+    else
+        a.dout[3 * off + (int64_t)(c - 1) * SZ + rem] = v;
+}
+
+int upload_gaunt(shg_ctx *c)
+{
+    if (c->gaunt_idx) return 0;
+    GauntTable G = build_gaunt_table(AAB_LA, AAB_LT);
+    std::vector<int32_t> idx, lm;
+    std::vector<double> gg;
+    const int maxmm = (2 * AAB_LA + 1) * (2 * AAB_LT + 1);
+    idx.assign((size_t)(AAB_LA + 1) * (AAB_LT + 1) * maxmm * 2, 0);
+    for (int la = 0; la <= AAB_LA; ++la)
+        for (int lt = 0; lt <= AAB_LT; ++lt)
+            for (int ma = -la; ma <= la; ++ma)
+                for (int mt = -lt; mt <= lt; ++mt) {
+                    const auto &ent = G.at(la, lt, ma, mt);
+                    size_t slot = ((size_t)(la * (AAB_LT + 1) + lt) * maxmm + (ma + la) * (2 * lt + 1) + (mt + lt)) * 2;
+                    idx[slot] = (int32_t)gg.size();
+                    idx[slot + 1] = (int32_t)ent.size();
+                    for (const auto &e : ent) {
+                        lm.push_back(e.L);
+                        lm.push_back(e.M);
+                        gg.push_back(e.g);
+                    }
+                }
+    HIP_TRY(c, hipMalloc((void **)&c->gaunt_idx, idx.size() * sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&c->gaunt_lm, lm.size() * sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&c->gaunt_g, gg.size() * sizeof(double)));
+    HIP_TRY(c, hipMemcpy(c->gaunt_idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->gaunt_lm, lm.data(), lm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->gaunt_g, gg.data(), gg.size() * sizeof(double), hipMemcpyHostToDevice));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux, const int32_t *triples, int64_t n,
+                       const int64_t *out_off, double *out, double *dout)
+{
+    const char *what = "shg_aab";
+    if (!c) return SHG_EINVAL;
+    if (n < 0) return set_err(c, SHG_EINVAL, "%s: n < 0", what);
+    if (n >= (int64_t)1 << 31) return set_err(c, SHG_EINVAL, "%s: n >= 2^31 triples per call", what);
+    int rc = check_shells(c, orb, what);
+    if (!rc) rc = check_shells(c, aux, what);
+    if (rc) return rc;
+    if (n == 0) return 0;
+    if (!triples || !out_off || !out) return set_err(c, SHG_EINVAL, "%s: NULL pointer argument", what);
+    if ((rc = upload_gaunt(c))) return rc;
+    const bool deriv = dout != nullptr;
+    const int D = deriv ? 1 : 0, NC = deriv ? 4 : 1;
+    hipStream_t s = c->stream;
+    if ((rc = grow(c, c->keys, c->keys_cap, (size_t)n))) return rc;
+    if ((rc = grow(c, c->order, c->order_cap, (size_t)n))) return rc;
+    int32_t *hist = c->bins, *cursor = c->bins + (NBINS_MAX + 1);
+    hipLaunchKernelGGL(k_fill_i32, dim3((AAB_NCLASS + 1 + 255) / 256), dim3(256), 0, s, hist, 0, AAB_NCLASS + 1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->err, 0, 1);
+    if ((rc = prep_shells(c, orb, AAB_LA, c->w, c->w_cap))) return rc;
+    if ((rc = prep_shells(c, aux, AAB_LT, c->w2, c->w2_cap))) return rc;
+    unsigned gb = (unsigned)((n + 256 * 16 - 1) / (256 * 16));
+    hipLaunchKernelGGL(k_aab_classify, dim3(gb), dim3(256), 0, s, n, triples, orb->nshell, orb->center, orb->l,
+                       aux->nshell, aux->center, aux->l, c->keys, hist, c->err);
+    hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(256), 0, s, hist, AAB_NCLASS, cursor, cursor);
+    HIP_TRY(c, hipMemcpyAsync(c->host_rb, cursor, (AAB_NCLASS + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(c->host_rb + AAB_NCLASS + 1, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(256), 0, s, n, c->keys, cursor, c->order);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if ((rc = decode_err(c, c->host_rb[AAB_NCLASS + 1], what))) return rc;
+    std::vector<int32_t> starts(c->host_rb, c->host_rb + AAB_NCLASS + 1);
+
+    if ((rc = grow(c, c->Pbuf, c->Pbuf_cap, (size_t)AAB_CHUNK * AAB_PSTRIDE))) return rc;
+    const aab_rad_fn *rtab = rad_table();
+    const int maxmm = (2 * AAB_LA + 1) * (2 * AAB_LT + 1);
+    for (int la = 0; la <= AAB_LA; ++la)
+        for (int lt = 0; lt <= AAB_LT; ++lt)
+            for (int lb = 0; lb <= AAB_LB; ++lb) {
+                const int key = (la * (AAB_LT + 1) + lt) * (AAB_LB + 1) + lb;
+                const int64_t b0 = starts[key], b1 = starts[key + 1];
+                if (b1 <= b0) continue;
+                const int lamin = la > lt ? la - lt : lt - la, lamax = la + lt, NB = 2 * lb + 1;
+                int64_t ys = 0;
+                for (int L = lamin; L <= lamax; L += 2) ys += (int64_t)(2 * L + 1) * NB;
+                const int64_t chunk = std::min<int64_t>(AAB_CHUNK, b1 - b0);
+                if ((rc = grow(c, c->Yv, c->Yv_cap, (size_t)(chunk * ys)))) return rc;
+                if (deriv && (rc = grow(c, c->Yd, c->Yd_cap, (size_t)(3 * chunk * ys)))) return rc;
+                for (int64_t c0 = b0; c0 < b1; c0 += chunk) {
+                    const int64_t cn = std::min<int64_t>(chunk, b1 - c0);
+                    AabRadArgs ra{triples, c->order, orb->center, orb->nprim, orb->prim_off, orb->exps, c->w,
+                                  aux->nprim, aux->prim_off, aux->exps, c->w2, c->Pbuf, c0, c0, cn};
+                    rtab[key * 2 + D](s, ra);
+                    int64_t loff = 0;
+                    for (int L = lamin, iL = 0; L <= lamax; L += 2, ++iL) {
+                        TileArgs ta{};
+                        ta.order = c->order;
+                        ta.center = orb->center;
+                        ta.out = c->Yv;
+                        ta.dout = deriv ? c->Yd : nullptr;
+                        ta.triples = triples;
+                        ta.P = c->Pbuf;
+                        ta.pstride = AAB_PSTRIDE;
+                        ta.poff = iL * 8;
+                        ta.ybase = c0;
+                        ta.ys = ys;
+                        ta.yoff = loff;
+                        TileShape shp = default_shape(L, lb, deriv, 64, 48 * 1024);
+                        tile_table(L)[lb * 2 + D](s, ta, c0, cn, shp);
+                        loff += (int64_t)(2 * L + 1) * NB;
+                    }
+                    GauntArgs ga{c->order, out_off, c->gaunt_idx + (size_t)(la * (AAB_LT + 1) + lt) * maxmm * 2,
+                                 c->gaunt_lm, c->gaunt_g, c->Yv, deriv ? c->Yd : nullptr, out, dout, c0, cn, ys,
+                                 la, lt, lb, NC, lamin};
+                    const int64_t nthreads = cn * NC * (2 * la + 1) * (2 * lt + 1) * NB;
+                    hipLaunchKernelGGL(k_aab_gaunt, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, s, ga);
+                }
+            }
+    HIP_TRY(c, hipGetLastError());
+    return 0;
+}

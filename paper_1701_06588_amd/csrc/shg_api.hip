@@ -9,79 +9,16 @@
 
 #include "../../include/shg.h"
 #include "boys_table.h"
+#include "shg_ctx.h"
 #include "shg_kernels.h"
 
 using namespace shg;
 
-// error bits raised on the device
-enum { ERR_SHELL_L = 1, ERR_SHELL_K = 2, ERR_SHELL_EXP = 4, ERR_PAIR_INDEX = 8, ERR_AAB_CENTER = 16,
-       ERR_AAB_L = 32 };
-
-struct shg_ctx {
-    hipStream_t stream = nullptr;
-    int device = 0;
-    double *boys = nullptr;          // Boys grid
-    // growable scratch
-    double *w = nullptr;  size_t w_cap = 0;          // folded weights
-    double *w2 = nullptr; size_t w2_cap = 0;         // second shell table (aab aux)
-    int32_t *keys = nullptr; size_t keys_cap = 0;
-    int32_t *order = nullptr; size_t order_cap = 0;
-    TileShape shape[5][LMAX + 1][LMAX + 1][2];      // tile shape per (op, la, lb, deriv), autotuned
-    char arch[64] = {0};
-    double tune_ms[5][LMAX + 1][LMAX + 1][2] = {};
-    // optional per-launch timing with HIP events (shg_profile_*)
-    int prof_on = 0;
-    hipEvent_t ev[NCLASS + 3] = {};   // [0] binning start, [1] binning end, [2+cls], [NCLASS+2] classes start
-    double prof_ms[NCLASS][2] = {};
-    int64_t prof_launches[NCLASS][2] = {}, prof_pairs[NCLASS][2] = {};
-    double prof_bin_ms = 0;
-    int64_t prof_bin_calls = 0;
-    int32_t *bins = nullptr;         // [2][NBINS_MAX + 1]: histogram, then cursors
-    int32_t *err = nullptr;          // device error flag
-    int32_t *host_rb = nullptr;      // pinned read-back: class starts + error
-    char msg[512] = {0};
-};
-
-static char g_create_msg[512];
-static constexpr int NBINS_MAX = 8192;
-
-static int set_err(shg_ctx *c, int code, const char *fmt, ...)
-{
-    char *dst = c ? c->msg : g_create_msg;
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(dst, 512, fmt, ap);
-    va_end(ap);
-    return code;
+namespace shg {
+char g_create_msg[512];
 }
 
-#define HIP_TRY(ctx, call)                                                                     \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return set_err(ctx, SHG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));   \
-    } while (0)
-
-template <class T>
-static int grow(shg_ctx *c, T *&p, size_t &cap, size_t need)
-{
-    if (need <= cap) return 0;
-    if (p) {
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        HIP_TRY(c, hipFree(p));
-        p = nullptr;
-        cap = 0;
-    }
-    size_t n = need + need / 4 + 64;
-    hipError_t e = hipMalloc((void **)&p, n * sizeof(T));
-    if (e != hipSuccess) {
-        p = nullptr;
-        return set_err(c, SHG_ENOMEM, "hipMalloc(%zu bytes) failed: %s", n * sizeof(T), hipGetErrorString(e));
-    }
-    cap = n;
-    return 0;
-}
-
+namespace shg {
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
@@ -203,6 +140,8 @@ __global__ __launch_bounds__(BIN_TPB) void k_scatter(int64_t n, const int32_t *k
     }
 }
 
+}  // namespace shg
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
@@ -265,7 +204,8 @@ extern "C" const char *shg_last_error(const shg_ctx *c) { return c ? c->msg : g_
 // ---------------------------------------------------------------------------
 // helpers shared by the entry points
 // ---------------------------------------------------------------------------
-static int check_shells(shg_ctx *c, const shg_shells *sh, const char *what)
+namespace shg {
+int check_shells(shg_ctx *c, const shg_shells *sh, const char *what)
 {
     if (!sh) return set_err(c, SHG_EINVAL, "%s: shell table is NULL", what);
     if (sh->nshell < 0 || sh->nprim_total < 0)
@@ -275,7 +215,7 @@ static int check_shells(shg_ctx *c, const shg_shells *sh, const char *what)
     return 0;
 }
 
-static int prep_shells(shg_ctx *c, const shg_shells *sh, int lmax, double *&w, size_t &cap)
+int prep_shells(shg_ctx *c, const shg_shells *sh, int lmax, double *&w, size_t &cap)
 {
     int rc = grow(c, w, cap, (size_t)sh->nprim_total + 1);
     if (rc) return rc;
@@ -285,7 +225,7 @@ static int prep_shells(shg_ctx *c, const shg_shells *sh, int lmax, double *&w, s
     return 0;
 }
 
-static int decode_err(shg_ctx *c, int32_t e, const char *what)
+int decode_err(shg_ctx *c, int32_t e, const char *what)
 {
     if (!e) return 0;
     return set_err(c, SHG_EINVAL, "%s: invalid input:%s%s%s%s%s%s", what, (e & ERR_SHELL_L) ? " shell l out of range;" : "",
@@ -295,6 +235,8 @@ static int decode_err(shg_ctx *c, int32_t e, const char *what)
                    (e & ERR_AAB_CENTER) ? " a and a~ of a triple are on different centers;" : "",
                    (e & ERR_AAB_L) ? " l of a triple outside the supported range;" : "");
 }
+
+}  // namespace shg
 
 static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
                         const int64_t *out_off, double *out, double *dout, bool deriv)
@@ -563,10 +505,4 @@ extern "C" int shg_tuning_load(shg_ctx *c, const char *path)
     return applied;
 }
 
-extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux, const int32_t *triples, int64_t n,
-                       const int64_t *out_off, double *out, double *dout)
-{
-    if (!c) return SHG_EINVAL;
-    (void)orb; (void)aux; (void)triples; (void)n; (void)out_off; (void)out; (void)dout;
-    return set_err(c, SHG_EINVAL, "shg_aab: not built yet");
-}
+

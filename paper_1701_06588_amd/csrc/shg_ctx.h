@@ -1,0 +1,105 @@
+// shg_ctx.h -- library-private context and helpers shared by the translation
+// units of libshg.so (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/shg.h"
+#include "shg_kernels.h"
+
+// error bits raised on the device
+enum { ERR_SHELL_L = 1, ERR_SHELL_K = 2, ERR_SHELL_EXP = 4, ERR_PAIR_INDEX = 8, ERR_AAB_CENTER = 16,
+       ERR_AAB_L = 32 };
+
+using shg::NCLASS;
+using shg::LMAX;
+using shg::TileShape;
+
+struct shg_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double *boys = nullptr;          // Boys grid
+    // growable scratch
+    double *w = nullptr;  size_t w_cap = 0;          // folded weights
+    double *w2 = nullptr; size_t w2_cap = 0;         // second shell table (aab aux)
+    int32_t *keys = nullptr; size_t keys_cap = 0;
+    int32_t *order = nullptr; size_t order_cap = 0;
+    TileShape shape[5][LMAX + 1][LMAX + 1][2];      // tile shape per (op, la, lb, deriv), autotuned
+    char arch[64] = {0};
+    double tune_ms[5][LMAX + 1][LMAX + 1][2] = {};
+    // optional per-launch timing with HIP events (shg_profile_*)
+    int prof_on = 0;
+    hipEvent_t ev[NCLASS + 3] = {};   // [0] binning start, [1] binning end, [2+cls], [NCLASS+2] classes start
+    double prof_ms[NCLASS][2] = {};
+    int64_t prof_launches[NCLASS][2] = {}, prof_pairs[NCLASS][2] = {};
+    double prof_bin_ms = 0;
+    int64_t prof_bin_calls = 0;
+    // three-index overlap: Gaunt table (uploaded on first use) and scratch
+    int32_t *gaunt_idx = nullptr;    // [(la*7 + lt)][(ma+la)(2lt+1) + mt+lt] -> {start, count}
+    int32_t *gaunt_lm = nullptr;     // entries: {L, M}
+    double *gaunt_g = nullptr;       // entries: coefficient
+    double *Pbuf = nullptr; size_t Pbuf_cap = 0;   // P^(k)_La per triple
+    double *Yv = nullptr; size_t Yv_cap = 0;       // two-center blocks (La|lb) per triple
+    double *Yd = nullptr; size_t Yd_cap = 0;       // and their d/dR_a
+    int32_t *bins = nullptr;         // [2][NBINS_MAX + 1]: histogram, then cursors
+    int32_t *err = nullptr;          // device error flag
+    int32_t *host_rb = nullptr;      // pinned read-back: class starts + error
+    char msg[512] = {0};
+};
+
+namespace shg {
+
+extern char g_create_msg[512];
+constexpr int NBINS_MAX = 8192;
+
+inline int set_err(shg_ctx *c, int code, const char *fmt, ...)
+{
+    char *dst = c ? c->msg : g_create_msg;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(dst, 512, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                     \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return set_err(ctx, SHG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+template <class T>
+inline int grow(shg_ctx *c, T *&p, size_t &cap, size_t need)
+{
+    if (need <= cap) return 0;
+    if (p) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipFree(p));
+        p = nullptr;
+        cap = 0;
+    }
+    size_t n = need + need / 4 + 64;
+    hipError_t e = hipMalloc((void **)&p, n * sizeof(T));
+    if (e != hipSuccess) {
+        p = nullptr;
+        return set_err(c, SHG_ENOMEM, "hipMalloc(%zu bytes) failed: %s", n * sizeof(T), hipGetErrorString(e));
+    }
+    cap = n;
+    return 0;
+}
+
+
+// helpers and small kernels defined in shg_api.hip
+int check_shells(shg_ctx *c, const shg_shells *sh, const char *what);
+int prep_shells(shg_ctx *c, const shg_shells *sh, int lmax, double *&w, size_t &cap);
+int decode_err(shg_ctx *c, int32_t e, const char *what);
+__global__ void k_fill_i32(int32_t *p, int32_t v, int n);
+__global__ void k_scan_bins(const int32_t *hist, int nb, int32_t *starts, int32_t *cursor);
+__global__ void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor, int32_t *order);
+
+}  // namespace shg

@@ -43,6 +43,14 @@ struct TileArgs {
     double *out, *dout;
     double omega;
     int op;
+    // three-index overlap mode (triples != nullptr): items are (a, a~, b)
+    // triples; phase 1 loads O^(k) = P^(k)_La from P[(pos - ybase) * pstride +
+    // poff + k] and block `pos` goes to out[(pos - ybase) * ys + yoff] (scratch
+    // Y blocks of one chunk of a triple class)
+    const int32_t *triples;
+    const double *P;
+    int pstride, poff;
+    int64_t ybase, ys, yoff;
 };
 
 // tile shape: TP pairs (64, 128 or 256) and rows_pp block rows per LDS pass
@@ -67,11 +75,24 @@ __device__ __forceinline__ void radial_rt(int op, double a, double b, double R2,
 // optimiser: placed between block elements it stops values of one element from
 // being shared with (and kept live for) the next, which bounds the register
 // footprint of the large classes at the cost of recomputing a few W entries.
-template <int L, int NK>
+constexpr bool row_used(int l, int LA, int LB, bool D)
+{
+    int jm = cmin(LA, LB) + (D ? 1 : 0);
+    return (l <= LA && l >= LA - jm) || (l <= LB && l >= LB - jm);
+}
+
+template <int LA, int LB, bool D, int L, int NK>
 __device__ __forceinline__ void reg_fence(RTab<L> &R, double (&O)[NK], double (&X)[3])
 {
+    static_for<0, L + 1>([&](auto LL) {
+        constexpr int l = decltype(LL)::value;
+        if constexpr (row_used(l, LA, LB, D)) {
 #pragma unroll
-    for (int k = 0; k < (L + 1) * (L + 2) / 2; ++k) asm volatile("" : "+v"(R.c[k]), "+v"(R.s[k]));
+            for (int m = 0; m <= l; ++m) asm volatile("" : "+v"(R.c[ridx(l, m)]));
+#pragma unroll
+            for (int m = 1; m <= l; ++m) asm volatile("" : "+v"(R.s[ridx(l, m)]));
+        }
+    });
 #pragma unroll
     for (int k = 0; k < NK; ++k) asm volatile("" : "+v"(O[k]));
     asm volatile("" : "+v"(X[0]), "+v"(X[1]), "+v"(X[2]));
@@ -98,7 +119,16 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
     const int tid = threadIdx.x;
 
     // ---- phase 1: radial terms and contraction, G lanes per shell pair ----
-    {
+    // (classes with l_a > LMAX only occur as L_a blocks of the three-index overlap)
+    if (LA > LMAX || a.triples) {
+        // (a b a~) mode: O^(k) = P^(k)_La was computed per triple by k_aab_radial
+        for (int i = tid; i < tcount; i += TILE_THREADS) {
+            const int64_t pos = tstart + i;
+#pragma unroll
+            for (int k = 0; k < PK::NK; ++k) sO[i * 8 + k] = a.P[(pos - a.ybase) * a.pstride + a.poff + k];
+            sOff[i] = (pos - a.ybase) * a.ys + a.yoff;
+        }
+    } else if constexpr (LA <= LMAX) {
         const int G = TILE_THREADS / TP;
         const int i = tid / G, g = tid - (tid / G) * G;
         const bool live = i < tcount;
@@ -142,7 +172,14 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
     double X[3], O[PK::NK];
     {
         const int p = a.order[tstart + (live ? i : 0)];
-        const int sa = a.pairs[2 * (int64_t)p], sb = a.pairs[2 * (int64_t)p + 1];
+        int sa, sb;
+        if (a.triples) {
+            sa = a.triples[3 * (int64_t)p];
+            sb = a.triples[3 * (int64_t)p + 2];
+        } else {
+            sa = a.pairs[2 * (int64_t)p];
+            sb = a.pairs[2 * (int64_t)p + 1];
+        }
         X[0] = a.center[3 * sa] - a.center[3 * sb];
         X[1] = a.center[3 * sa + 1] - a.center[3 * sb + 1];
         X[2] = a.center[3 * sa + 2] - a.center[3 * sb + 2];
@@ -159,7 +196,7 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
             constexpr int E = decltype(EE)::value;
             constexpr int IA = E / NB, IB = E % NB;
             if (IA >= r0 && IA < r1 && ((E - r0 * NB) % EW) == es) {
-                reg_fence(R, O, X);
+                reg_fence<LA, LB, D>(R, O, X);
                 double res[NC];
                 pair_elem<LA, LB, IA, IB, D>(R, O, X, res);
                 if (live) {
@@ -225,11 +262,33 @@ inline TileShape default_shape(int la, int lb, bool D, int tp, int lds_budget)
     return TileShape{tp, rows};
 }
 
-// dispatch tables (one translation unit per l_a): tile_table_la<l_a>()[lb * 2 + D]
+// dispatch tables (one translation unit per l_a): tile_table_la<l_a>()[lb * 2 + D];
+// l_a = 0..4 cover lb = 0..4 (two-center classes), l_a = 5..9 cover lb = 0..3
+// (the L_a blocks of the three-index overlap)
 const tile_fn *tile_table_la0();
 const tile_fn *tile_table_la1();
 const tile_fn *tile_table_la2();
 const tile_fn *tile_table_la3();
 const tile_fn *tile_table_la4();
+const tile_fn *tile_table_la5();
+const tile_fn *tile_table_la6();
+const tile_fn *tile_table_la7();
+const tile_fn *tile_table_la8();
+const tile_fn *tile_table_la9();
+inline const tile_fn *tile_table(int la)
+{
+    switch (la) {
+    case 0: return tile_table_la0();
+    case 1: return tile_table_la1();
+    case 2: return tile_table_la2();
+    case 3: return tile_table_la3();
+    case 4: return tile_table_la4();
+    case 5: return tile_table_la5();
+    case 6: return tile_table_la6();
+    case 7: return tile_table_la7();
+    case 8: return tile_table_la8();
+    default: return tile_table_la9();
+    }
+}
 
 }  // namespace shg

@@ -466,4 +466,97 @@ SHG_HD SHG_INL void pair_block_from_O(const double *O, const double X[3], double
     });
 }
 
+// ---------------------------------------------------------------------------
+// Three-index overlap (a b a~), Sec. II.D. For each L_a in |la-lt|..la+lt
+// (step 2) the block (a b a~) is a sum over the Gaunt expansion of two-center
+// blocks (L_a, M_a | lb, mb) whose contracted monopole is P^(k)_{La} (eq. Pa_aba)
+// instead of O^(k); the primitive radial terms are (0_a'|r_a^{2m}|0_b)^(k)
+// (eqs. sra2ms, I_jab, devsra2ms) with alpha' = alpha + alpha~.
+// ---------------------------------------------------------------------------
+constexpr double cbinom(int n, int k) { return (k < 0 || k > n) ? 0.0 : cfact(n) / (cfact(k) * cfact(n - k)); }
+// rising factorial (L)_j = L (L+1) ... (L+j-1) = (L+j-1)!/(L-1)!, equal to 1 for j = 0
+// and to 0 for L = 0, j >= 1
+constexpr double crising(int L, int j) { double f = 1; for (int i = 0; i < j; ++i) f *= (L + i); return f; }
+
+template <int LA, int LT, int LB, bool D>
+struct AabK {
+    static constexpr int LAMIN = cabs(LA - LT), LAMAX = LA + LT, NLA = (LAMAX - LAMIN) / 2 + 1;
+    static constexpr int PMAX = cmin(LA, LT);
+    static constexpr int KMIN = cmax(LAMIN, LB), KT = LAMAX + LB + (D ? 1 : 0), NKT = KT - KMIN + 1;
+    static constexpr int PSTRIDE = 32;   // per triple in the P buffer: iLa * 8 + (k - max(La, lb))
+};
+
+// (0_a'|r_a^{2m}|0_b)^(k) for m = 0..PMAX and k = KMIN..KT:
+//   pi^(3/2) e^{-rho R^2} / (2^m c^(m+3/2)) sum_i binom(k,i) (-rho)^(k-i) sum_{j>=i} d^i I_j / d(R^2)^i
+//   I_j = 2^j (2m+1)!! binom(m,j) / (2j+1)!! * (beta^2/c)^j R^(2j),  c = alpha'+beta, rho = alpha' beta / c
+template <int PMAX, int KMIN, int KT>
+SHG_HD SHG_INL void sra2m(double ap, double b, double R2, double (&t)[PMAX + 1][KT - KMIN + 1])
+{
+    const double c = ap + b, ic = 1.0 / c, rho = ap * b * ic, u = b * b * ic;
+    double nr[KT + 1];
+    nr[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= KT; ++k) nr[k] = nr[k - 1] * (-rho);
+    double base = PI_1_5 * exp(-rho * R2) * ic * sqrt(ic);
+    static_for<0, PMAX + 1>([&](auto MM) {
+        constexpr int M = decltype(MM)::value;
+        double C[M + 1];
+        double uj = 1.0;
+#pragma unroll
+        for (int j = 0; j <= M; ++j) {
+            C[j] = (cpow2(j) * cdfact(2 * M + 1) * cbinom(M, j) / cdfact(2 * j + 1)) * uj;
+            uj *= u;
+        }
+        double S[M + 1];   // S^(i)(R^2) = sum_{j>=i} C_j j!/(j-i)! (R^2)^(j-i)
+#pragma unroll
+        for (int i = 0; i <= M; ++i) {
+            double acc = C[M] * (cfact(M) / cfact(M - i));
+#pragma unroll
+            for (int j = M - 1; j >= i; --j) acc = fma(acc, R2, C[j] * (cfact(j) / cfact(j - i)));
+            S[i] = acc;
+        }
+#pragma unroll
+        for (int k = KMIN; k <= KT; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i <= (M < k ? M : k); ++i) acc = fma(cbinom(k, i) * nr[k - i], S[i], acc);
+            t[M][k - KMIN] = base * acc;
+        }
+        base *= 0.5 * ic;
+    });
+}
+
+// P[iLa][k - max(La, lb)] += contribution of one primitive triple (eq. Pa_aba):
+//   lambda K_La N_la N_lb N_lt c_alpha c_beta c_alpha~ / ((2 alpha')^La (2 beta)^lb)
+//   * sum_j binom(p,j) (La)_j / alpha'^j (0_a'|r_a^{2(p-j)}|0_b)^(k),  p = (la+lt-La)/2
+// `wabt` = N_la c_alpha * N_lt c_alpha~ * N_lb c_beta / (2 beta)^lb.
+template <int LA, int LT, int LB, bool D>
+SHG_HD SHG_INL void aab_accumulate(double ap, double b, double R2, double wabt,
+                                   double (&P)[AabK<LA, LT, LB, D>::NLA][8])
+{
+    using AK = AabK<LA, LT, LB, D>;
+    double t[AK::PMAX + 1][AK::NKT];
+    sra2m<AK::PMAX, AK::KMIN, AK::KT>(ap, b, R2, t);
+    const double iap = 1.0 / ap, i2ap = 0.5 * iap;
+    static_for<0, AK::NLA>([&](auto II) {
+        constexpr int I = decltype(II)::value;
+        constexpr int LAc = AK::LAMIN + 2 * I, p = (LA + LT - LAc) / 2;
+        constexpr double lamK = csqrt(4.0 * PI * (2 * LAc + 1) / ((2.0 * LA + 1) * (2 * LT + 1)));
+        constexpr int KLO = cmax(LAc, LB), KHI = LAc + LB + (D ? 1 : 0);
+        double coef = wabt * lamK;
+#pragma unroll
+        for (int q = 0; q < LAc; ++q) coef *= i2ap;
+#pragma unroll
+        for (int k = KLO; k <= KHI; ++k) {
+            double sacc = 0.0, apj = 1.0;
+#pragma unroll
+            for (int j = 0; j <= p; ++j) {
+                sacc = fma(cbinom(p, j) * crising(LAc, j) * apj, t[p - j][k - AK::KMIN], sacc);
+                apj *= iap;
+            }
+            P[I][k - KLO] = fma(coef, sacc, P[I][k - KLO]);
+        }
+    });
+}
+
 }  // namespace shg
