@@ -109,6 +109,36 @@ int shg_aab(shg_ctx *ctx, const shg_shells *orb, const shg_shells *aux,
             const int32_t *triples, int64_t n, const int64_t *out_off,
             double *out, double *dout);
 
+/* ---- batched path ------------------------------------------------------- */
+
+/* A plan fixes one evaluation: shell table, operator, pair list, offsets and
+ * output buffers (all device pointers, kept by reference, owned by the caller
+ * and required to outlive the plan). Creation runs shg_pairs / shg_pairs_deriv
+ * once (dout NULL: values only), which validates the input and bins the pairs
+ * by class, copies the class-sorted order, builds a tile work queue ordered
+ * heaviest class first and, unless SHG_PLAN_NO_GRAPH, records the evaluation
+ * (shell preparation + class kernels) in a hipGraph. Execution replays it with
+ * no host synchronisation and no binning; new centers, exponents or raw
+ * coefficients written into the same buffers are picked up, but the shells'
+ * l and K and the pair list must not change (they are not re-validated).
+ *   flags: SHG_PLAN_PERSISTENT  one persistent class-binned kernel over the
+ *                               tile queue instead of one launch per class
+ *          SHG_PLAN_NO_GRAPH    enqueue the kernels on every execute */
+#define SHG_PLAN_PERSISTENT 1u
+#define SHG_PLAN_NO_GRAPH   2u
+typedef struct shg_plan shg_plan;
+int  shg_plan_create(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
+                     const int32_t *pairs, int64_t n, const int64_t *out_off,
+                     double *out, double *dout, unsigned flags, shg_plan **plan);
+int  shg_plan_execute(shg_plan *plan);        /* asynchronous on the ctx stream */
+/* Times both modes `reps` times with HIP events (synchronous), keeps the
+ * faster one (re-recording the graph) and reports both times (host pointers,
+ * nullable). */
+int  shg_plan_autotune(shg_plan *plan, int reps, double *ms_per_class, double *ms_persistent);
+int  shg_plan_set_mode(shg_plan *plan, int persistent);
+int  shg_plan_mode(const shg_plan *plan);     /* 0 per-class launches, 1 persistent */
+void shg_plan_destroy(shg_plan *plan);
+
 /* ---- tuning and timing ------------------------------------------------- */
 
 /* Tile shape used by the per-class launches of operator op for class

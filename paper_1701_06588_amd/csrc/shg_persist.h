@@ -1,0 +1,80 @@
+// shg_persist.h -- persistent, class-binned kernel of the batched path.
+//
+// One launch evaluates every tile of a plan: each workgroup repeatedly takes
+// the next tile index from a device counter (one atomic per tile), reads the
+// tile's class and range from the work queue and runs the class's tile code
+// (tile_pairs, shared with the per-class kernels). All classes of one
+// derivative flavour live in this one kernel; the queue is ordered heaviest
+// class first so that the tail of the launch is made of light tiles. Every
+// workgroup exits once the counter passes the number of tiles.
+#pragma once
+#include "shg_kernels.h"
+
+namespace shg {
+
+struct QTile {
+    int32_t cls;      // la * 5 + lb
+    int32_t count;    // pairs in the tile (<= shape.tp)
+    int64_t start;    // first sorted position
+};
+
+// dynamic LDS limit of the persistent kernel (160 KiB minus its static LDS)
+constexpr int PERSIST_MAX_SMEM = 160 * 1024 - 256;
+
+struct ShapeTable {
+    TileShape s[NCLASS];
+};
+
+template <bool D>
+__global__ __launch_bounds__(TILE_THREADS) void k_persist(TileArgs a, const QTile *__restrict__ q, int ntiles,
+                                                          int *counter, ShapeTable shapes)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int s_t;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = s_t;
+        __syncthreads();
+        if (t >= ntiles) break;
+        const QTile tile = q[t];
+        const TileShape sh = shapes.s[tile.cls];
+        static_for<0, NCLASS>([&](auto CC) {
+            constexpr int C = decltype(CC)::value;
+            if (tile.cls == C) tile_pairs<C / (LMAX + 1), C % (LMAX + 1), D>(a, tile.start, tile.count, sh, smem);
+        });
+    }
+}
+
+typedef void (*persist_fn)(hipStream_t, int grid, size_t smem, const TileArgs &, const QTile *, int, int *,
+                           const ShapeTable &);
+typedef int (*persist_occ_fn)(size_t smem);
+
+template <bool D>
+void launch_persist(hipStream_t s, int grid, size_t smem, const TileArgs &a, const QTile *q, int ntiles, int *counter,
+                    const ShapeTable &shapes)
+{
+    hipLaunchKernelGGL(k_persist<D>, dim3(grid), dim3(TILE_THREADS), smem, s, a, q, ntiles, counter, shapes);
+}
+
+// also raises the kernel's dynamic-LDS limit (done here, before any graph
+// capture, rather than inside the launch)
+template <bool D>
+int persist_occupancy(size_t smem)
+{
+    (void)hipFuncSetAttribute((const void *)k_persist<D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              PERSIST_MAX_SMEM);
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<D>, TILE_THREADS, smem);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();   // do not leave a sticky error behind
+        return 1;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+// defined in shg_persist_d0.hip / shg_persist_d1.hip
+void persist_entry_d0(persist_fn *f, persist_occ_fn *occ);
+void persist_entry_d1(persist_fn *f, persist_occ_fn *occ);
+
+}  // namespace shg

@@ -1,0 +1,258 @@
+// shg_plan.hip -- batched path: a plan bins a fixed pair list once, orders its
+// tiles into a work queue and records the evaluation in a hipGraph that can be
+// replayed (picking up new centers, exponents or coefficients written into the
+// same device buffers) without any host synchronisation.
+//
+// Two execution modes, chosen at creation (SHG_PLAN_PERSISTENT) or by
+// shg_plan_autotune:
+//   per-class   the per-class k_tile launches of the plain path, graph-captured
+//   persistent  one k_persist launch over a heaviest-class-first tile queue
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "shg_ctx.h"
+#include "shg_persist.h"
+
+using namespace shg;
+
+struct shg_plan {
+    shg_ctx *ctx = nullptr;
+    shg_shells sh{};
+    int op = 0;
+    double omega = 0;
+    const int32_t *pairs = nullptr;
+    int64_t n = 0;
+    const int64_t *out_off = nullptr;
+    double *out = nullptr, *dout = nullptr;
+    int deriv = 0;
+    int mode = 0;                     // 0 per-class launches, 1 persistent
+    int32_t *order = nullptr;         // class-sorted pair ids (plan-owned)
+    double *w = nullptr;              // folded weights (plan-owned)
+    QTile *queue = nullptr;
+    int ntiles = 0;
+    int *counter = nullptr;
+    int grid = 0;
+    size_t smem = 0;
+    ShapeTable shapes{};
+    int64_t cls_start[NCLASS + 1] = {};
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static int plan_enqueue(shg_plan *p, hipStream_t s)
+{
+    shg_ctx *c = p->ctx;
+    const shg_shells *sh = &p->sh;
+    if (sh->nshell > 0)
+        hipLaunchKernelGGL(k_prep_shells, dim3((sh->nshell + 255) / 256), dim3(256), 0, s, sh->nshell, sh->l, sh->nprim,
+                           sh->prim_off, sh->exps, sh->coefs, sh->nprim_total, LMAX, p->w, c->err);
+    TileArgs ta{p->pairs, p->order, sh->center, sh->nprim, sh->prim_off, sh->exps, p->w, c->boys, p->out_off, p->out,
+                p->dout, p->omega, p->op};
+    if (p->mode == 0) {
+        for (int cls = 0; cls < NCLASS; ++cls) {
+            int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
+            if (b1 <= b0) continue;
+            tile_table(cls / (LMAX + 1))[(cls % (LMAX + 1)) * 2 + p->deriv](s, ta, b0, b1 - b0, p->shapes.s[cls]);
+        }
+    } else if (p->ntiles > 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
+        persist_fn f;
+        persist_occ_fn occ;
+        if (p->deriv) persist_entry_d1(&f, &occ);
+        else persist_entry_d0(&f, &occ);
+        f(s, p->grid, p->smem, ta, p->queue, p->ntiles, p->counter, p->shapes);
+    }
+    HIP_TRY(c, hipGetLastError());
+    return 0;
+}
+
+static void plan_free_graph(shg_plan *p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+static int plan_capture(shg_plan *p)
+{
+    shg_ctx *c = p->ctx;
+    plan_free_graph(p);
+    if (!p->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(c, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = plan_enqueue(p, p->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return set_err(c, SHG_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    p->graph = g;
+    HIP_TRY(c, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    return 0;
+}
+
+// builds the heaviest-class-first tile queue for the current shapes
+static int plan_build_queue(shg_plan *p)
+{
+    shg_ctx *c = p->ctx;
+    std::vector<QTile> q;
+    std::vector<std::pair<double, int>> cls_cost;
+    for (int cls = 0; cls < NCLASS; ++cls) {
+        int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
+        double per_pair = (double)(2 * la + 1) * (2 * lb + 1) * (p->deriv ? 4 : 1) + 4.0 * (la + lb + 1);
+        cls_cost.push_back({-per_pair, cls});
+    }
+    std::sort(cls_cost.begin(), cls_cost.end());
+    size_t smem = 0;
+    for (auto &cc : cls_cost) {
+        int cls = cc.second;
+        int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
+        const TileShape &t = p->shapes.s[cls];
+        int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
+        if (b1 > b0) {
+            size_t b = (size_t)t.tp * 72 + (size_t)t.tp * (p->deriv ? 4 : 1) * t.rows_pp * (2 * lb + 1) * 8;
+            smem = std::max(smem, b);
+        }
+        (void)la;
+        for (int64_t s0 = b0; s0 < b1; s0 += t.tp) q.push_back(QTile{cls, (int32_t)std::min<int64_t>(t.tp, b1 - s0), s0});
+    }
+    if (q.size() >= (size_t)1 << 31) return set_err(c, SHG_EINVAL, "plan: too many tiles");
+    if (p->queue) { HIP_TRY(c, hipFree(p->queue)); p->queue = nullptr; }
+    p->ntiles = (int)q.size();
+    p->smem = smem;
+    if (smem > (size_t)PERSIST_MAX_SMEM && p->mode == 1)
+        return set_err(c, SHG_EINVAL, "plan: tile shapes need %zu bytes of LDS, more than the persistent kernel allows",
+                       smem);
+    if (!q.empty()) {
+        HIP_TRY(c, hipMalloc((void **)&p->queue, q.size() * sizeof(QTile)));
+        HIP_TRY(c, hipMemcpy(p->queue, q.data(), q.size() * sizeof(QTile), hipMemcpyHostToDevice));
+    }
+    persist_fn f;
+    persist_occ_fn occ;
+    if (p->deriv) persist_entry_d1(&f, &occ);
+    else persist_entry_d0(&f, &occ);
+    hipDeviceProp_t prop;
+    HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+    // the per-class kernels raise their LDS limit on first launch; make sure that
+    // happened before a graph capture by launching nothing here but the query
+    int per_cu = occ(p->smem);
+    p->grid = std::max(1, std::min(p->ntiles, prop.multiProcessorCount * per_cu));
+    return 0;
+}
+
+extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
+                               int64_t n, const int64_t *out_off, double *out, double *dout, unsigned flags,
+                               shg_plan **plan)
+{
+    if (!c || !plan) return SHG_EINVAL;
+    *plan = nullptr;
+    const bool deriv = dout != nullptr;
+    // evaluate once through the plain path: validates the input and bins the pairs
+    int rc = deriv ? shg_pairs_deriv(c, sh, op, omega, pairs, n, out_off, out, dout)
+                   : shg_pairs(c, sh, op, omega, pairs, n, out_off, out);
+    if (rc) return rc;
+    shg_plan *p = new (std::nothrow) shg_plan();
+    if (!p) return set_err(c, SHG_ENOMEM, "shg_plan_create: out of host memory");
+    p->ctx = c;
+    p->sh = *sh;
+    p->op = (int)op;
+    p->omega = omega;
+    p->pairs = pairs;
+    p->n = n;
+    p->out_off = out_off;
+    p->out = out;
+    p->dout = dout;
+    p->deriv = deriv ? 1 : 0;
+    p->mode = (flags & SHG_PLAN_PERSISTENT) ? 1 : 0;
+    for (int cls = 0; cls <= NCLASS; ++cls) p->cls_start[cls] = n > 0 ? c->host_rb[cls * 64] : 0;
+    for (int cls = 0; cls < NCLASS; ++cls) p->shapes.s[cls] = c->shape[op][cls / (LMAX + 1)][cls % (LMAX + 1)][p->deriv];
+    auto fail = [&](int code) { shg_plan_destroy(p); return code; };
+    hipError_t e = hipMalloc((void **)&p->order, std::max<int64_t>(n, 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->w, std::max<int64_t>(sh->nprim_total, 1) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->counter, 64 * sizeof(int));
+    if (e != hipSuccess) return fail(set_err(c, SHG_ENOMEM, "shg_plan_create: %s", hipGetErrorString(e)));
+    if (n > 0) {
+        e = hipMemcpyAsync(p->order, c->order, n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(set_err(c, SHG_EDEVICE, "shg_plan_create: %s", hipGetErrorString(e)));
+    }
+    if ((rc = plan_build_queue(p))) return fail(rc);
+    if (!(flags & SHG_PLAN_NO_GRAPH) && (rc = plan_capture(p))) return fail(rc);
+    *plan = p;
+    return 0;
+}
+
+extern "C" int shg_plan_execute(shg_plan *p)
+{
+    if (!p) return SHG_EINVAL;
+    shg_ctx *c = p->ctx;
+    if (p->exec) {
+        HIP_TRY(c, hipGraphLaunch(p->exec, c->stream));
+        return 0;
+    }
+    return plan_enqueue(p, c->stream);
+}
+
+extern "C" int shg_plan_set_mode(shg_plan *p, int persistent)
+{
+    if (!p) return SHG_EINVAL;
+    if (persistent && p->smem > (size_t)PERSIST_MAX_SMEM)
+        return set_err(p->ctx, SHG_EINVAL, "plan: tile shapes need more LDS than the persistent kernel allows");
+    p->mode = persistent ? 1 : 0;
+    if (p->graph || p->exec) {
+        HIP_TRY(p->ctx, hipStreamSynchronize(p->ctx->stream));
+        return plan_capture(p);
+    }
+    return 0;
+}
+
+extern "C" int shg_plan_autotune(shg_plan *p, int reps, double *ms_per_class, double *ms_persistent)
+{
+    if (!p) return SHG_EINVAL;
+    shg_ctx *c = p->ctx;
+    if (reps < 1) reps = 1;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    float t[2] = {0, 0};
+    const int nmodes = p->smem > (size_t)PERSIST_MAX_SMEM ? 1 : 2;
+    for (int mode = 0; mode < nmodes; ++mode) {
+        p->mode = mode;
+        int rc = plan_enqueue(p, c->stream);   // warm-up
+        if (rc) return rc;
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r)
+            if ((rc = plan_enqueue(p, c->stream))) return rc;
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        HIP_TRY(c, hipEventElapsedTime(&t[mode], e0, e1));
+        t[mode] /= reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms_per_class) *ms_per_class = t[0];
+    if (ms_persistent) *ms_persistent = t[1];
+    p->mode = (nmodes == 2 && t[1] < t[0]) ? 1 : 0;
+    if (p->graph || p->exec) return plan_capture(p);
+    return 0;
+}
+
+extern "C" int shg_plan_mode(const shg_plan *p) { return p ? p->mode : SHG_EINVAL; }
+
+extern "C" void shg_plan_destroy(shg_plan *p)
+{
+    if (!p) return;
+    if (p->ctx) (void)hipStreamSynchronize(p->ctx->stream);
+    plan_free_graph(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    (void)hipFree(p->order);
+    (void)hipFree(p->w);
+    (void)hipFree(p->queue);
+    (void)hipFree(p->counter);
+    delete p;
+}

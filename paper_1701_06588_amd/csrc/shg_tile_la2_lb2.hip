@@ -1,0 +1,9 @@
+// k_tile instantiations for class (la, lb) = (2, 2), without and with derivatives
+#include "shg_kernels.h"
+namespace shg {
+const tile_fn *tile_fns_la2_lb2()
+{
+    static const tile_fn t[2] = {&launch_tile<2, 2, false>, &launch_tile<2, 2, true>};
+    return t;
+}
+}  // namespace shg

@@ -1,0 +1,9 @@
+// k_tile instantiations for class (la, lb) = (6, 2), without and with derivatives
+#include "shg_kernels.h"
+namespace shg {
+const tile_fn *tile_fns_la6_lb2()
+{
+    static const tile_fn t[2] = {&launch_tile<6, 2, false>, &launch_tile<6, 2, true>};
+    return t;
+}
+}  // namespace shg

@@ -18,7 +18,8 @@ OPS = {"overlap": 0, "coulomb": 1, "erf": 2, "erfc": 3, "gauss": 4}
 ERRORS = {-1: "SHG_EINVAL", -2: "SHG_ENOMEM", -3: "SHG_EDEVICE"}
 EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pairs_deriv", "shg_aab",
            "shg_set_tile_shape", "shg_get_tile_shape", "shg_autotune", "shg_tuning_save", "shg_tuning_load",
-           "shg_profile_enable", "shg_profile_read")
+           "shg_profile_enable", "shg_profile_read", "shg_plan_create", "shg_plan_execute",
+           "shg_plan_autotune", "shg_plan_set_mode", "shg_plan_mode", "shg_plan_destroy")
 
 
 class ShgShells(C.Structure):
@@ -66,6 +67,14 @@ def load_library(path: str = LIB_PATH):
     lib.shg_profile_enable.argtypes = [P, I]
     lib.shg_profile_read.argtypes = [P, I, I, I, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64)]
+    lib.shg_plan_create.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, P, P, P, C.c_uint,
+                                    C.POINTER(C.c_void_p)]
+    lib.shg_plan_execute.argtypes = [P]
+    lib.shg_plan_autotune.argtypes = [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.shg_plan_set_mode.argtypes = [P, I]
+    lib.shg_plan_mode.argtypes = [P]
+    lib.shg_plan_destroy.argtypes = [P]
+    lib.shg_plan_destroy.restype = None
     _lib = lib
     return lib
 
@@ -172,6 +181,50 @@ class Engine:
         rc = self.lib.shg_aab(self.ctx, C.byref(orb.c), C.byref(aux.c), _ptr(triples), n, _ptr(out_off),
                               _ptr(out), _ptr(dout))
         self._check(rc)
+
+
+PLAN_PERSISTENT = 1
+PLAN_NO_GRAPH = 2
+
+
+class Plan:
+    """A recorded evaluation (shg_plan_*): fixed shells, operator, pairs and outputs."""
+
+    def __init__(self, engine: "Engine", dsh: DeviceShells, op: str, omega: float, pairs, out_off, out, dout=None,
+                 flags: int = 0):
+        self.engine = engine
+        self.keep = (dsh, pairs, out_off, out, dout)   # the plan references these buffers
+        h = C.c_void_p()
+        engine._check(engine.lib.shg_plan_create(engine.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs),
+                                                 int(pairs.shape[0]), _ptr(out_off), _ptr(out), _ptr(dout),
+                                                 int(flags), C.byref(h)))
+        self.h = h
+
+    def execute(self):
+        self.engine._check(self.engine.lib.shg_plan_execute(self.h))
+
+    def autotune(self, reps=3):
+        a, b = C.c_double(), C.c_double()
+        self.engine._check(self.engine.lib.shg_plan_autotune(self.h, reps, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def set_mode(self, persistent: bool):
+        self.engine._check(self.engine.lib.shg_plan_set_mode(self.h, int(persistent)))
+
+    @property
+    def mode(self) -> str:
+        return "persistent" if self.engine.lib.shg_plan_mode(self.h) == 1 else "per-class"
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.engine.lib.shg_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def run_workload_pairs(engine: Engine, w, op: str, deriv: bool):
