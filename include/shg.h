@@ -137,7 +137,66 @@ int  shg_plan_execute(shg_plan *plan);        /* asynchronous on the ctx stream 
 int  shg_plan_autotune(shg_plan *plan, int reps, double *ms_per_class, double *ms_persistent);
 int  shg_plan_set_mode(shg_plan *plan, int persistent);
 int  shg_plan_mode(const shg_plan *plan);     /* 0 per-class launches, 1 persistent */
+/* ids of the pairs a screened plan skips, written to the host array ids
+ * (capacity cap, nullable); returns how many there are */
+int64_t shg_plan_skipped(const shg_plan *plan, int32_t *ids, int64_t cap);
+/* number of pairs a plan evaluates (after screening) and their algorithmic
+ * bytes (8 (2la+1)(2lb+1)(1 or 4) + 16 per pair); host pointers */
+int  shg_plan_stats(const shg_plan *plan, int64_t *kept, int64_t *alg_bytes);
+/* mean duration in ms of the plan's evaluation kernels alone (no shell
+ * preparation), timed with HIP events over `reps` runs; synchronous */
+int  shg_plan_kernel_ms(shg_plan *plan, int reps, double *ms);
 void shg_plan_destroy(shg_plan *plan);
+
+/* ---- prescreening ------------------------------------------------------ */
+
+/* Learned predictor of log10 max|block| (12 features -> 3 x 64 SiLU -> 1;
+ * bf16 weights, fp32 accumulation; inference on bf16 MFMA, training on the
+ * library's own forward/backward/Adam kernels). Parameters: 9217 fp32 master
+ * values (layout W1[64][12], b1, W2[64][64], b2, W3[64][64], b3, w4[64], b4). */
+typedef struct shg_mlp shg_mlp;
+int  shg_mlp_create(shg_ctx *ctx, uint64_t seed, shg_mlp **mlp);      /* He-initialised */
+void shg_mlp_destroy(shg_mlp *mlp);
+/* host arrays of 9217 floats (nullable): copy out the master parameters and/or
+ * replace them (replacing resets the Adam state) */
+int  shg_mlp_params(shg_mlp *mlp, float *host_out, const float *host_in);
+/* feature standardisation (mean, std) and training range [lo, hi] (host arrays
+ * of 12, lo/hi nullable); pairs with a feature outside the range fall back to
+ * the analytic bound */
+int  shg_mlp_set_norm(shg_mlp *mlp, const float *mean, const float *std, const float *lo, const float *hi);
+/* calibration margin (log10 units) added to predictions before comparing with tau */
+int  shg_mlp_set_margin(shg_mlp *mlp, float margin);
+/* one Adam step on a batch: X [B][12] and y [B] device fp32; pinball loss at
+ * `quantile` on y - prediction; loss_out (device float, nullable) receives
+ * the summed per-sample loss */
+int  shg_mlp_train_step(shg_mlp *mlp, const float *X, const float *y, int B, float lr, float quantile,
+                        float *loss_out);
+/* gradient of the mean loss (device [9217], nullable) without updating */
+int  shg_mlp_grad(shg_mlp *mlp, const float *X, const float *y, int B, float quantile, float *grad_out,
+                  float *loss_out);
+/* prediction for n feature rows (device): pred [n] fp32, in_range [n] int32 */
+int  shg_mlp_predict(shg_mlp *mlp, const float *X, int64_t n, float *pred, int32_t *in_range);
+int  shg_mlp_save(shg_mlp *mlp, const char *path);
+int  shg_mlp_load(shg_mlp *mlp, const char *path);
+
+/* The 12 screening features of each pair (device fp32 [n][12]: la, lb,
+ * log10 alpha_min/max of a and of b, R, log10(1 + rho_min R^2), log10 bound,
+ * erfc flag, omega R, log10(sum|w_a| sum|w_b|)) and log10 of the conservative
+ * analytic bound on max|block| (device fp32 [n]). */
+int  shg_screen_features(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
+                         const int32_t *pairs, int64_t n, float *feat, float *log10_bound);
+/* log10 max|block| (clamped at -30) of evaluated blocks (training targets) */
+int  shg_block_logmax(shg_ctx *ctx, const shg_shells *sh, const int32_t *pairs, int64_t n,
+                      const int64_t *out_off, const double *out, float *y);
+/* Screened plan: as shg_plan_create, then every pair whose analytic bound is
+ * below tau, or (mlp non-NULL, features in range) whose prediction plus the
+ * model margin is below log10(tau), is skipped: its block is set to zero once
+ * here and never evaluated again; executions evaluate the kept pairs only.
+ * *n_skipped (host, nullable) receives the number of skipped pairs. */
+int  shg_plan_create_screened(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
+                              const int32_t *pairs, int64_t n, const int64_t *out_off,
+                              double *out, double *dout, unsigned flags, double tau,
+                              shg_mlp *mlp, shg_plan **plan, int64_t *n_skipped);
 
 /* ---- tuning and timing ------------------------------------------------- */
 

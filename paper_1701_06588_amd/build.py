@@ -22,12 +22,24 @@ FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-Wall", "-Wno-
          "-mllvm", "-enable-gvn-memdep=false"]
 
 
+def _deps(path: str, seen=None) -> set:
+    """The file and every local header it includes, recursively."""
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for line in open(path, errors="ignore"):
+        line = line.strip()
+        if line.startswith("#include") and '"' in line:
+            inc = line.split('"')[1]
+            _deps(os.path.normpath(os.path.join(os.path.dirname(path), inc)), seen)
+    return seen
+
+
 def _compile(src: str, verbose: bool, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
     if incremental and os.path.exists(obj):
-        deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(CSRC, "*.inc")) + \
-            [os.path.join(os.path.dirname(HERE), "include", "shg.h")]
-        if all(os.path.getmtime(d) <= os.path.getmtime(obj) for d in deps if os.path.exists(d)):
+        if all(os.path.getmtime(d) <= os.path.getmtime(obj) for d in _deps(src)):
             return obj
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     if verbose:

@@ -194,6 +194,13 @@ extern "C" void shg_destroy(shg_ctx *c)
     (void)hipFree(c->keys);
     (void)hipFree(c->order);
     (void)hipFree(c->bins);
+    (void)hipFree(c->stats);
+    (void)hipFree(c->Pbuf);
+    (void)hipFree(c->Yv);
+    (void)hipFree(c->Yd);
+    (void)hipFree(c->gaunt_idx);
+    (void)hipFree(c->gaunt_lm);
+    (void)hipFree(c->gaunt_g);
     (void)hipFree(c->err);
     if (c->host_rb) (void)hipHostFree(c->host_rb);
     delete c;

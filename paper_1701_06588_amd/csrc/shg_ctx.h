@@ -45,6 +45,7 @@ struct shg_ctx {
     double *Pbuf = nullptr; size_t Pbuf_cap = 0;   // P^(k)_La per triple
     double *Yv = nullptr; size_t Yv_cap = 0;       // two-center blocks (La|lb) per triple
     double *Yd = nullptr; size_t Yd_cap = 0;       // and their d/dR_a
+    double *stats = nullptr; size_t stats_cap = 0;  // per-shell screening statistics
     int32_t *bins = nullptr;         // [2][NBINS_MAX + 1]: histogram, then cursors
     int32_t *err = nullptr;          // device error flag
     int32_t *host_rb = nullptr;      // pinned read-back: class starts + error
@@ -104,5 +105,9 @@ __global__ void k_prep_shells(int nshell, const int32_t *l, const int32_t *nprim
                               int32_t *err);
 __global__ void k_scan_bins(const int32_t *hist, int nb, int32_t *starts, int32_t *cursor);
 __global__ void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor, int32_t *order);
+// screening decisions (shg_screen.hip): keep[i] = 0 if pair i may be skipped;
+// work: n * 15 floats of scratch
+int screen_pairs(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
+                 double tau, shg_mlp *mlp, int32_t *keep, float *work);
 
 }  // namespace shg

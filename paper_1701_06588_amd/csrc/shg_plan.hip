@@ -40,6 +40,7 @@ struct shg_plan {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<int32_t> skipped;     // pair ids removed by screening
 };
 
 static int plan_enqueue(shg_plan *p, hipStream_t s)
@@ -187,6 +188,83 @@ extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, doub
     return 0;
 }
 
+__global__ void k_zero_blocks(int64_t ns, const int32_t *ids, const int32_t *pairs, const int32_t *l,
+                              const int64_t *out_off, double *out, double *dout)
+{
+    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (i >= ns) return;
+    const int p = ids[i];
+    const int sz = (2 * l[pairs[2 * (int64_t)p]] + 1) * (2 * l[pairs[2 * (int64_t)p + 1]] + 1);
+    const int64_t off = out_off[p];
+    for (int e = threadIdx.x % 64; e < sz; e += 64) out[off + e] = 0.0;
+    if (dout)
+        for (int e = threadIdx.x % 64; e < 3 * sz; e += 64) dout[3 * off + e] = 0.0;
+}
+
+extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op op, double omega,
+                                        const int32_t *pairs, int64_t n, const int64_t *out_off, double *out,
+                                        double *dout, unsigned flags, double tau, shg_mlp *mlp, shg_plan **plan,
+                                        int64_t *n_skipped)
+{
+    if (!c || !plan) return SHG_EINVAL;
+    *plan = nullptr;
+    if (!(tau > 0.0)) return set_err(c, SHG_EINVAL, "shg_plan_create_screened: tau must be positive");
+    shg_plan *p = nullptr;
+    int rc = shg_plan_create(c, sh, op, omega, pairs, n, out_off, out, dout, flags | SHG_PLAN_NO_GRAPH, &p);
+    if (rc) return rc;
+    auto fail = [&](int code) { shg_plan_destroy(p); return code; };
+    int64_t nskip = 0;
+    if (n > 0) {
+        int32_t *keep = nullptr;
+        float *work = nullptr;
+        HIP_TRY(c, hipMalloc((void **)&keep, n * sizeof(int32_t)));
+        if (hipMalloc((void **)&work, (size_t)n * 15 * sizeof(float)) != hipSuccess) {
+            (void)hipFree(keep);
+            return fail(set_err(c, SHG_ENOMEM, "shg_plan_create_screened: out of device memory"));
+        }
+        rc = screen_pairs(c, sh, op, omega, pairs, n, tau, mlp, keep, work);
+        std::vector<int32_t> hkeep(n), horder(n);
+        if (!rc && (hipMemcpy(hkeep.data(), keep, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+                    hipMemcpy(horder.data(), p->order, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess))
+            rc = set_err(c, SHG_EDEVICE, "shg_plan_create_screened: read-back failed");
+        (void)hipFree(work);
+        (void)hipFree(keep);
+        if (rc) return fail(rc);
+        // stable compaction of the class-sorted order; skipped ids collected
+        std::vector<int32_t> korder, skipped;
+        korder.reserve(n);
+        int64_t new_start[NCLASS + 1];
+        for (int cls = 0; cls < NCLASS; ++cls) {
+            new_start[cls] = (int64_t)korder.size();
+            for (int64_t q = p->cls_start[cls]; q < p->cls_start[cls + 1]; ++q) {
+                int32_t id = horder[q];
+                if (hkeep[id]) korder.push_back(id);
+                else skipped.push_back(id);
+            }
+        }
+        new_start[NCLASS] = (int64_t)korder.size();
+        nskip = (int64_t)skipped.size();
+        p->skipped = skipped;
+        if (!korder.empty())
+            HIP_TRY(c, hipMemcpy(p->order, korder.data(), korder.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        for (int cls = 0; cls <= NCLASS; ++cls) p->cls_start[cls] = new_start[cls];
+        if (nskip > 0) {
+            int32_t *ids = nullptr;
+            HIP_TRY(c, hipMalloc((void **)&ids, nskip * sizeof(int32_t)));
+            HIP_TRY(c, hipMemcpy(ids, skipped.data(), nskip * sizeof(int32_t), hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(k_zero_blocks, dim3((unsigned)((nskip + 3) / 4)), dim3(256), 0, c->stream, nskip, ids,
+                               pairs, sh->l, out_off, out, dout);
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            (void)hipFree(ids);
+        }
+        if ((rc = plan_build_queue(p))) return fail(rc);
+    }
+    if (!(flags & SHG_PLAN_NO_GRAPH) && (rc = plan_capture(p))) return fail(rc);
+    if (n_skipped) *n_skipped = nskip;
+    *plan = p;
+    return 0;
+}
+
 extern "C" int shg_plan_execute(shg_plan *p)
 {
     if (!p) return SHG_EINVAL;
@@ -243,6 +321,76 @@ extern "C" int shg_plan_autotune(shg_plan *p, int reps, double *ms_per_class, do
 }
 
 extern "C" int shg_plan_mode(const shg_plan *p) { return p ? p->mode : SHG_EINVAL; }
+
+// ids of the pairs a screened plan skips (host array of capacity cap); returns
+// their number (the full count even when cap is smaller)
+extern "C" int64_t shg_plan_skipped(const shg_plan *p, int32_t *ids, int64_t cap)
+{
+    if (!p) return SHG_EINVAL;
+    int64_t n = (int64_t)p->skipped.size();
+    if (ids)
+        for (int64_t i = 0; i < n && i < cap; ++i) ids[i] = p->skipped[i];
+    return n;
+}
+
+// kept pairs and their algorithmic bytes (output values [+ d/dR_a] + 8 bytes of
+// pair indices + 8 bytes of offset per pair), host pointers
+extern "C" int shg_plan_stats(const shg_plan *p, int64_t *kept, int64_t *alg_bytes)
+{
+    if (!p || !kept || !alg_bytes) return SHG_EINVAL;
+    int64_t k = 0, b = 0;
+    for (int cls = 0; cls < NCLASS; ++cls) {
+        int64_t cnt = p->cls_start[cls + 1] - p->cls_start[cls];
+        int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
+        k += cnt;
+        b += cnt * ((int64_t)8 * (2 * la + 1) * (2 * lb + 1) * (p->deriv ? 4 : 1) + 16);
+    }
+    *kept = k;
+    *alg_bytes = b;
+    return 0;
+}
+
+// average duration (ms) of the evaluation kernels alone (persistent kernel or
+// the per-class launches, without the shell preparation), timed with HIP events
+// over `reps` enqueues on the ctx stream; synchronous
+extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
+{
+    if (!p || !ms || reps < 1) return SHG_EINVAL;
+    shg_ctx *c = p->ctx;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    TileArgs ta{p->pairs, p->order, p->sh.center, p->sh.nprim, p->sh.prim_off, p->sh.exps, p->w, c->boys,
+                p->out_off, p->out, p->dout, p->omega, p->op};
+    double tot = 0;
+    for (int r = 0; r < reps; ++r) {
+        if (p->mode == 1) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, 1);
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+        if (p->mode == 1) {
+            persist_fn f;
+            persist_occ_fn occ;
+            if (p->deriv) persist_entry_d1(&f, &occ);
+            else persist_entry_d0(&f, &occ);
+            if (p->ntiles > 0) f(c->stream, p->grid, p->smem, ta, p->queue, p->ntiles, p->counter, p->shapes);
+        } else {
+            for (int cls = 0; cls < NCLASS; ++cls) {
+                int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
+                if (b1 > b0)
+                    tile_table(cls / (LMAX + 1))[(cls % (LMAX + 1)) * 2 + p->deriv](c->stream, ta, b0, b1 - b0,
+                                                                                   p->shapes.s[cls]);
+            }
+        }
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        float t = 0;
+        HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
+        tot += t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = tot / reps;
+    return 0;
+}
 
 extern "C" void shg_plan_destroy(shg_plan *p)
 {

@@ -1,0 +1,782 @@
+// shg_screen.hip -- prescreening of shell pairs: a conservative analytic bound
+// on max|block| and a learned predictor (small MLP, bf16 weights, fp32
+// accumulation) of log10 max|block|; screened plans evaluate only kept pairs.
+//
+// Analytic bound (values, two-center (a|O|b)): with X = R_a - R_b, R = |X|,
+//   |block| <= sum_j |O^(la+lb-j)| Cq(la, lb, j) R^(la+lb-2j)          (eq. final_r12int_ab)
+// where Cq bounds A_a A_b |Qhat_j| / R^(la+lb-2j) over all (m_a, m_b) using
+// |R^{c/s}_{l,m}(X)| <= R^l / sqrt((l-|m|)!(l+|m|)!) (|C_lm(X)| <= R^l), and
+// |O^(k)| <= sum |w_a w_b| |(0|O|0)^(k)| is bounded per operator (Table S1) with
+//   Coulomb  F_k(T) <= 1/(2k+1) and F_k(T) <= (2k-1)!!/2^(k+1) sqrt(pi/T^(2k+1)),
+//            alpha + beta >= 2 sqrt(alpha beta):
+//            near = 2 pi^(5/2) 2^-(k+1/2) / (2k+1) * Sc_a(k) Sc_b(k),  Sc(k) = sum|w| a^(k/2-5/4)
+//            far  = 2 pi^3 (2k-1)!!/2^(k+1) * Sf_a Sf_b / R^(2k+1),   Sf    = sum|w| a^(-3/2)
+//   erf      <= the Coulomb bound; erfc <= twice the Coulomb bound
+//   overlap  pi^(3/2) 2^(-3/2-k) So_a(k) So_b(k) e^{-rho_min R^2},  So(k) = sum|w| a^(k/2-3/4)
+//   Gaussian pi^3 omega^(-3/2) 2^(-3/2-k) So_a(k) So_b(k) e^{-omega rho_min R^2/(rho_min+omega)}
+// (rho_min from the most diffuse exponents: rho and the exponent are increasing in both).
+//
+// MLP: 12 standardised features -> 64 -> 64 -> 64 -> 1, SiLU hidden activations.
+// Inference on MFMA (v_mfma_f32_16x16x16 bf16, fp32 accumulate): a wave takes 16
+// pairs; activations go through LDS between layers (bf16). Training in fp32 VALU
+// on the same bf16-rounded weights and activations (straight-through rounding):
+// forward (thread per sample), backward deltas (thread per sample), weight
+// gradients as batch reductions (thread per weight, no atomics), Adam.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <random>
+#include <vector>
+
+#include "shg_ctx.h"
+
+using namespace shg;
+
+namespace {
+
+constexpr int NF = 12;          // features
+constexpr int NH = 64;          // hidden width
+constexpr int NPARAM = NH * NF + NH + NH * NH + NH + NH * NH + NH + NH + 1;   // 9217
+// parameter offsets in the flat fp32 array
+constexpr int P_W1 = 0, P_B1 = P_W1 + NH * NF, P_W2 = P_B1 + NH, P_B2 = P_W2 + NH * NH, P_W3 = P_B2 + NH,
+              P_B3 = P_W3 + NH * NH, P_W4 = P_B3 + NH, P_B4 = P_W4 + NH;
+constexpr int STAT = 32;        // doubles per shell in the statistics table
+constexpr int KB = 10;          // k = 0..9 moments
+
+// ---------------------------------------------------------------------------
+// per-shell statistics: alpha_min, alpha_max, sum|w|, Sf, Sc[k], So[k]
+// ---------------------------------------------------------------------------
+__global__ void k_shell_stats(int nshell, const int32_t *nprim, const int64_t *prim_off, const double *exps,
+                              const double *w, double *st)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nshell) return;
+    double amin = 1e300, amax = 0, sw = 0, sf = 0, sc[KB], so[KB];
+    for (int k = 0; k < KB; ++k) sc[k] = so[k] = 0;
+    for (int q = 0; q < nprim[i]; ++q) {
+        double a = exps[prim_off[i] + q], aw = fabs(w[prim_off[i] + q]);
+        amin = fmin(amin, a);
+        amax = fmax(amax, a);
+        sw += aw;
+        double la = log(a);
+        sf += aw * exp(-1.5 * la);
+        for (int k = 0; k < KB; ++k) {
+            sc[k] += aw * exp((0.5 * k - 1.25) * la);
+            so[k] += aw * exp((0.5 * k - 0.75) * la);
+        }
+    }
+    double *o = st + (size_t)i * STAT;
+    o[0] = amin;
+    o[1] = amax;
+    o[2] = sw;
+    o[3] = sf;
+    for (int k = 0; k < KB; ++k) {
+        o[4 + k] = sc[k];
+        o[4 + KB + k] = so[k];
+    }
+}
+
+struct BoundTab {
+    double cq[5][5][5];   // Cq(la, lb, j)
+};
+
+__device__ __forceinline__ double dfact_d(int n) { double f = 1; for (int i = n; i > 1; i -= 2) f *= i; return f; }
+
+// log10 of the analytic bound and the 12 features of one pair
+__global__ void k_bound_features(int64_t n, const int32_t *pairs, const double *center, const int32_t *l,
+                                 const double *st, int op, double omega, BoundTab bt, float *feat, float *logb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = pairs[2 * i], b = pairs[2 * i + 1];
+    const int la = l[a], lb = l[b];
+    const double X0 = center[3 * a] - center[3 * b], X1 = center[3 * a + 1] - center[3 * b + 1],
+                 X2 = center[3 * a + 2] - center[3 * b + 2];
+    const double R2 = X0 * X0 + X1 * X1 + X2 * X2, R = sqrt(R2);
+    const double *sa = st + (size_t)a * STAT, *sb = st + (size_t)b * STAT;
+    const double rmin = sa[0] * sb[0] / (sa[0] + sb[0]);
+    const double PI_ = 3.141592653589793238462643383279502884;
+    double bound = 0.0;
+    const int jm = la < lb ? la : lb;
+    for (int j = 0; j <= jm; ++j) {
+        const int k = la + lb - j, pw = la + lb - 2 * j;
+        double ob;
+        if (op == OP_OVERLAP || op == OP_GAUSS) {
+            ob = pow(2.0, -1.5 - k) * sa[4 + KB + k] * sb[4 + KB + k];
+            if (op == OP_OVERLAP) ob *= pow(PI_, 1.5) * exp(-rmin * R2);
+            else ob *= PI_ * PI_ * PI_ * pow(omega, -1.5) * exp(-omega * rmin * R2 / (rmin + omega));
+        } else {
+            double nearb = 2.0 * pow(PI_, 2.5) * pow(2.0, -(k + 0.5)) / (2 * k + 1) * sa[4 + k] * sb[4 + k];
+            double farb = R > 0 ? 2.0 * PI_ * PI_ * PI_ * dfact_d(2 * k - 1) * pow(2.0, -(k + 1)) * sa[3] * sb[3] *
+                                      pow(R, -(2.0 * k + 1))
+                                : 1e300;
+            ob = fmin(nearb, farb) * (op == OP_ERFC ? 2.0 : 1.0);
+        }
+        bound += ob * bt.cq[la][lb][j] * (pw == 0 ? 1.0 : pow(R, (double)pw));
+    }
+    const double lb10 = bound > 0 ? log10(bound) : -300.0;
+    logb[i] = (float)fmax(lb10, -300.0);
+    float *f = feat + i * NF;
+    f[0] = (float)la;
+    f[1] = (float)lb;
+    f[2] = (float)log10(sa[0]);
+    f[3] = (float)log10(sa[1]);
+    f[4] = (float)log10(sb[0]);
+    f[5] = (float)log10(sb[1]);
+    f[6] = (float)R;
+    f[7] = (float)log10(1.0 + rmin * R2);
+    f[8] = (float)fmax(lb10, -40.0);
+    f[9] = op == OP_ERFC ? 1.0f : 0.0f;
+    f[10] = (op == OP_ERF || op == OP_ERFC) ? (float)(omega * R) : 0.0f;
+    f[11] = (float)log10(sa[2] * sb[2]);
+}
+
+// log10 max|block| (clamped at -30) of evaluated blocks: the training target
+__global__ void k_block_logmax(int64_t n, const int32_t *pairs, const int32_t *l, const int64_t *out_off,
+                               const double *out, float *y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int la = l[pairs[2 * i]], lb = l[pairs[2 * i + 1]];
+    const int sz = (2 * la + 1) * (2 * lb + 1);
+    double m = 0;
+    for (int e = 0; e < sz; ++e) m = fmax(m, fabs(out[out_off[i] + e]));
+    y[i] = (float)fmax(m > 0 ? log10(m) : -30.0, -30.0);
+}
+
+// ---------------------------------------------------------------------------
+// bf16 helpers (round to nearest even)
+// ---------------------------------------------------------------------------
+__device__ __host__ inline uint16_t f2bf(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7fffffff) > 0x7f800000) return (uint16_t)((u >> 16) | 0x40);   // NaN stays NaN
+    u += 0x7fff + ((u >> 16) & 1);
+    return (uint16_t)(u >> 16);
+}
+__device__ __host__ inline float bf2f(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float x;
+    memcpy(&x, &u, 4);
+    return x;
+}
+__device__ inline float bfr(float x) { return bf2f(f2bf(x)); }
+__device__ inline float silu(float z) { return z / (1.0f + expf(-z)); }
+__device__ inline float dsilu(float z)
+{
+    float s = 1.0f / (1.0f + expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// bf16 copies of the weights (working copy) from the fp32 master parameters;
+// W1 is padded to 16 inputs for the MFMA layout
+__global__ void k_mlp_pack(const float *p, uint16_t *wb)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // layout: W1p [64][16], W2 [64][64], W3 [64][64]
+    if (t < NH * 16) {
+        int o = t / 16, i = t % 16;
+        wb[t] = i < NF ? f2bf(p[P_W1 + o * NF + i]) : 0;
+    } else if (t < NH * 16 + NH * NH) {
+        int u = t - NH * 16;
+        wb[t] = f2bf(p[P_W2 + u]);
+    } else if (t < NH * 16 + 2 * NH * NH) {
+        int u = t - NH * 16 - NH * NH;
+        wb[t] = f2bf(p[P_W3 + u]);
+    }
+}
+
+struct MlpNorm {
+    float mean[NF], inv_std[NF], lo[NF], hi[NF];
+};
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// inference: 256 threads = 4 waves, a wave evaluates 16 pairs per iteration.
+// MFMA 16x16x16 bf16 lane layout (checked on gfx950): A: lane l holds
+// A[l%16][4(l/16)+v]; B: lane l holds B[4(l/16)+v][l%16]; D: lane l holds
+// D[4(l/16)+v][l%16], v = 0..3.
+__global__ __launch_bounds__(256) void k_mlp_infer(int64_t n, const float *feat, const uint16_t *wb, const float *p,
+                                                   MlpNorm nm, float *pred, int32_t *in_range)
+{
+    __shared__ uint16_t sW[NH * 16 + 2 * NH * NH];          // 18 KiB
+    __shared__ float sB[3 * NH + NH + 1];
+    __shared__ uint16_t sAct[4][16][NH + 4];                 // per wave activation tile
+    for (int t = threadIdx.x; t < NH * 16 + 2 * NH * NH; t += 256) sW[t] = wb[t];
+    for (int t = threadIdx.x; t < NH; t += 256) {
+        sB[t] = p[P_B1 + t];
+        sB[NH + t] = p[P_B2 + t];
+        sB[2 * NH + t] = p[P_B3 + t];
+        sB[3 * NH + t] = bf2f(f2bf(p[P_W4 + t]));
+    }
+    if (threadIdx.x == 0) sB[4 * NH] = p[P_B4];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int64_t ntile = (n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+        const int64_t base = tile * 16;
+        // layer 1 input: A[i = pair][k = feature], lane holds pair r, features 4g..4g+3
+        short4_t a;
+        int ok = 1;
+        {
+            const int64_t pi = base + r;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int k = 4 * g + v;
+                float x = 0.0f;
+                if (k < NF && pi < n) {
+                    float f = feat[pi * NF + k];
+                    if (!(f >= nm.lo[k] && f <= nm.hi[k])) ok = 0;
+                    x = (f - nm.mean[k]) * nm.inv_std[k];
+                }
+                a[v] = (short)f2bf(x);
+            }
+        }
+        // in-range flag of pair r = AND over the 4 lane groups
+        ok &= __shfl_xor(ok, 16);
+        ok &= __shfl_xor(ok, 32);
+        float4_t acc[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            short4_t bw;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bw[v] = (short)sW[(16 * nt + r) * 16 + 4 * g + v];   // W1p[o][k]
+            acc[nt] = (float4_t){0, 0, 0, 0};
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[nt], 0, 0, 0);
+        }
+        const uint16_t *Wl[2] = {sW + NH * 16, sW + NH * 16 + NH * NH};
+#pragma unroll
+        for (int layer = 0; layer < 3; ++layer) {
+            // bias + SiLU, stage to LDS as bf16 in [pair][neuron]
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int i = 4 * g + v, o = 16 * nt + r;
+                    sAct[wv][i][o] = f2bf(silu(acc[nt][v] + sB[layer * NH + o]));
+                }
+            __builtin_amdgcn_wave_barrier();   // LDS accesses of one wave complete in order
+            if (layer == 2) break;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[nt] = (float4_t){0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                short4_t aa;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) aa[v] = (short)sAct[wv][r][16 * ks + 4 * g + v];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    short4_t bw;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) bw[v] = (short)Wl[layer][(16 * nt + r) * NH + 16 * ks + 4 * g + v];
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aa, bw, acc[nt], 0, 0, 0);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // output layer: y_i = w4 . a3_i + b4; lane (r, g) sums neurons 16 g' + r ... use the staged tile
+        float y = 0.0f;
+        if (lane < 16) {
+#pragma unroll 8
+            for (int o = 0; o < NH; ++o) y = fmaf(sB[3 * NH + o], bf2f(sAct[wv][lane][o]), y);
+            y += sB[4 * NH];
+            const int64_t pi = base + lane;
+            if (pi < n) {
+                pred[pi] = y;
+                in_range[pi] = ok;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ---- training (fp32 VALU, bf16-rounded weights and activations) ----------
+struct TrainBuf {
+    float *xh;      // [B][16] standardised, rounded inputs
+    float *z;       // [B][3][64] pre-activations
+    float *act;     // [B][3][64] rounded activations
+    float *dl;      // [B][3][64] deltas
+    float *gy;      // [B] dLoss/dy
+    float *loss;    // [B] per-sample loss
+};
+
+__global__ __launch_bounds__(128) void k_mlp_fwd(int B, const float *X, const float *Y, const float *p, MlpNorm nm,
+                                                 float q, TrainBuf tb)
+{
+    __shared__ float sP[NPARAM];
+    for (int t = threadIdx.x; t < NPARAM; t += 128) {
+        bool is_w = (t < P_B1) || (t >= P_W2 && t < P_B2) || (t >= P_W3 && t < P_B3) || (t >= P_W4 && t < P_B4);
+        sP[t] = is_w ? bfr(p[t]) : p[t];
+    }
+    __syncthreads();
+    const int b = blockIdx.x * 128 + threadIdx.x;
+    if (b >= B) return;
+    float x[NF], h[NH], h2[NH];
+    for (int k = 0; k < NF; ++k) {
+        x[k] = bfr((X[(int64_t)b * NF + k] - nm.mean[k]) * nm.inv_std[k]);
+        tb.xh[b * 16 + k] = x[k];
+    }
+    for (int o = 0; o < NH; ++o) {
+        float s = sP[P_B1 + o];
+        for (int k = 0; k < NF; ++k) s = fmaf(sP[P_W1 + o * NF + k], x[k], s);
+        tb.z[(b * 3 + 0) * NH + o] = s;
+        h[o] = bfr(silu(s));
+        tb.act[(b * 3 + 0) * NH + o] = h[o];
+    }
+    for (int layer = 1; layer < 3; ++layer) {
+        const int W = layer == 1 ? P_W2 : P_W3, Bo = layer == 1 ? P_B2 : P_B3;
+        for (int o = 0; o < NH; ++o) {
+            float s = sP[Bo + o];
+            for (int k = 0; k < NH; ++k) s = fmaf(sP[W + o * NH + k], h[k], s);
+            tb.z[(b * 3 + layer) * NH + o] = s;
+            h2[o] = bfr(silu(s));
+            tb.act[(b * 3 + layer) * NH + o] = h2[o];
+        }
+        for (int o = 0; o < NH; ++o) h[o] = h2[o];
+    }
+    float y = sP[P_B4];
+    for (int k = 0; k < NH; ++k) y = fmaf(sP[P_W4 + k], h[k], y);
+    // pinball loss at quantile q on r = target - prediction
+    const float rres = Y[b] - y;
+    tb.loss[b] = rres > 0 ? q * rres : (q - 1.0f) * rres;
+    tb.gy[b] = (rres > 0 ? -q : 1.0f - q) / (float)B;
+}
+
+__global__ __launch_bounds__(128) void k_mlp_bwd(int B, const float *p, TrainBuf tb)
+{
+    __shared__ float sP[NPARAM];
+    for (int t = threadIdx.x; t < NPARAM; t += 128) {
+        bool is_w = (t < P_B1) || (t >= P_W2 && t < P_B2) || (t >= P_W3 && t < P_B3) || (t >= P_W4 && t < P_B4);
+        sP[t] = is_w ? bfr(p[t]) : p[t];
+    }
+    __syncthreads();
+    const int b = blockIdx.x * 128 + threadIdx.x;
+    if (b >= B) return;
+    float d[NH], dn[NH];
+    const float gy = tb.gy[b];
+    for (int o = 0; o < NH; ++o) {
+        d[o] = gy * sP[P_W4 + o] * dsilu(tb.z[(b * 3 + 2) * NH + o]);
+        tb.dl[(b * 3 + 2) * NH + o] = d[o];
+    }
+    for (int layer = 2; layer >= 1; --layer) {
+        const int W = layer == 2 ? P_W3 : P_W2;
+        for (int k = 0; k < NH; ++k) {
+            float s = 0.0f;
+            for (int o = 0; o < NH; ++o) s = fmaf(sP[W + o * NH + k], d[o], s);
+            dn[k] = s * dsilu(tb.z[(b * 3 + layer - 1) * NH + k]);
+            tb.dl[(b * 3 + layer - 1) * NH + k] = dn[k];
+        }
+        for (int k = 0; k < NH; ++k) d[k] = dn[k];
+    }
+}
+
+// one thread per parameter: gradient as a reduction over the batch
+__global__ __launch_bounds__(256) void k_mlp_grad(int B, TrainBuf tb, float *grad)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= NPARAM) return;
+    float s = 0.0f;
+    if (t < P_B1) {                       // W1[o][k]: delta1[o] * xh[k]
+        int o = t / NF, k = t % NF;
+        for (int b = 0; b < B; ++b) s = fmaf(tb.dl[(b * 3 + 0) * NH + o], tb.xh[b * 16 + k], s);
+    } else if (t < P_W2) {                // b1
+        int o = t - P_B1;
+        for (int b = 0; b < B; ++b) s += tb.dl[(b * 3 + 0) * NH + o];
+    } else if (t < P_B2) {                // W2[o][k]: delta2[o] * act1[k]
+        int u = t - P_W2, o = u / NH, k = u % NH;
+        for (int b = 0; b < B; ++b) s = fmaf(tb.dl[(b * 3 + 1) * NH + o], tb.act[(b * 3 + 0) * NH + k], s);
+    } else if (t < P_W3) {
+        int o = t - P_B2;
+        for (int b = 0; b < B; ++b) s += tb.dl[(b * 3 + 1) * NH + o];
+    } else if (t < P_B3) {                // W3[o][k]: delta3[o] * act2[k]
+        int u = t - P_W3, o = u / NH, k = u % NH;
+        for (int b = 0; b < B; ++b) s = fmaf(tb.dl[(b * 3 + 2) * NH + o], tb.act[(b * 3 + 1) * NH + k], s);
+    } else if (t < P_W4) {
+        int o = t - P_B3;
+        for (int b = 0; b < B; ++b) s += tb.dl[(b * 3 + 2) * NH + o];
+    } else if (t < P_B4) {                // w4[k]: gy * act3[k]
+        int k = t - P_W4;
+        for (int b = 0; b < B; ++b) s = fmaf(tb.gy[b], tb.act[(b * 3 + 2) * NH + k], s);
+    } else {
+        for (int b = 0; b < B; ++b) s += tb.gy[b];
+    }
+    grad[t] = s;
+}
+
+__global__ void k_adam(float *p, float *m, float *v, const float *g, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NPARAM) return;
+    const float gg = g[t];
+    const float mm = b1 * m[t] + (1 - b1) * gg, vv = b2 * v[t] + (1 - b2) * gg * gg;
+    m[t] = mm;
+    v[t] = vv;
+    p[t] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+__global__ void k_sum_f32(int n, const float *x, float *out)
+{
+    __shared__ float sh[256];
+    float s = 0;
+    for (int i = threadIdx.x; i < n; i += 256) s += x[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// host: Cq(la, lb, j) bound of A_a A_b |Qhat_j| / R^(la+lb-2j) over (m_a, m_b)
+double rb_host(int l, int m)
+{
+    int mu = m < 0 ? -m : m;
+    if (l < 0 || mu > l) return 0.0;
+    double f = 1;
+    for (int i = 2; i <= l - mu; ++i) f *= i;
+    double g = 1;
+    for (int i = 2; i <= l + mu; ++i) g *= i;
+    return 1.0 / sqrt(f * g);
+}
+double wbound_host(int l, int mu, int t, int j, int k, int s)
+{
+    int lj = l - j;
+    if (s == 1 && k == 0) return 0.0;
+    if (t == 1 && mu == 0) return 0.0;
+    double half = (k == 0 && s == 0) ? 0.5 : 1.0;
+    return half * (rb_host(lj, mu - k) + rb_host(lj, mu + k));
+}
+BoundTab build_bound_table()
+{
+    BoundTab bt{};
+    for (int la = 0; la <= 4; ++la)
+        for (int lb = 0; lb <= 4; ++lb)
+            for (int j = 0; j <= (la < lb ? la : lb); ++j) {
+                double best = 0;
+                for (int ma = -la; ma <= la; ++ma)
+                    for (int mb = -lb; mb <= lb; ++mb) {
+                        int mua = ma < 0 ? -ma : ma, mub = mb < 0 ? -mb : mb, ta = ma < 0, tb = mb < 0;
+                        double fa = 1, fb = 1;
+                        for (int i = 2; i <= la + mua; ++i) fa *= i;
+                        for (int i = 2; i <= la - mua; ++i) fa *= i;
+                        for (int i = 2; i <= lb + mub; ++i) fb *= i;
+                        for (int i = 2; i <= lb - mub; ++i) fb *= i;
+                        double AA = sqrt((mua ? 2.0 : 1.0) * fa) * sqrt((mub ? 2.0 : 1.0) * fb);
+                        double pref = pow(2.0, la + lb - j);
+                        for (int i = 2 * j - 1; i > 1; i -= 2) pref *= i;
+                        double s = 0;
+                        for (int k = 0; k <= j; ++k) {
+                            double fjk = 1;
+                            for (int i = 2; i <= j + k; ++i) fjk *= i;
+                            for (int i = 2; i <= j - k; ++i) fjk *= i;
+                            double B = 1.0 / ((k ? 2.0 : 1.0) * fjk);
+                            for (int sc = 0; sc < 2; ++sc)
+                                s += B * wbound_host(la, mua, ta, j, k, sc) * wbound_host(lb, mub, tb, j, k, sc);
+                        }
+                        best = fmax(best, AA * pref * s);
+                    }
+                bt.cq[la][lb][j] = best * (1.0 + 1e-12);
+            }
+    return bt;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+struct shg_mlp {
+    shg_ctx *ctx = nullptr;
+    float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;   // fp32 master, Adam moments, gradient
+    uint16_t *wb = nullptr;                                         // bf16 working copy (packed)
+    MlpNorm norm{};
+    float margin = 0.0f;
+    int step = 0;
+    TrainBuf tb{};
+    int tb_cap = 0;
+    float *dsum = nullptr;
+};
+
+extern "C" int shg_mlp_create(shg_ctx *c, uint64_t seed, shg_mlp **out)
+{
+    if (!c || !out) return SHG_EINVAL;
+    *out = nullptr;
+    shg_mlp *m = new (std::nothrow) shg_mlp();
+    if (!m) return set_err(c, SHG_ENOMEM, "shg_mlp_create: out of host memory");
+    m->ctx = c;
+    std::vector<float> p(NPARAM, 0.0f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<float> nd(0.0f, 1.0f);
+    auto init = [&](int off, int fan_out, int fan_in) {
+        float s = sqrtf(2.0f / fan_in);
+        for (int i = 0; i < fan_out * fan_in; ++i) p[off + i] = nd(rng) * s;
+    };
+    init(P_W1, NH, NF);
+    init(P_W2, NH, NH);
+    init(P_W3, NH, NH);
+    init(P_W4, 1, NH);
+    for (int k = 0; k < NF; ++k) {
+        m->norm.mean[k] = 0.0f;
+        m->norm.inv_std[k] = 1.0f;
+        m->norm.lo[k] = -1e30f;
+        m->norm.hi[k] = 1e30f;
+    }
+    hipError_t e = hipMalloc((void **)&m->p, NPARAM * sizeof(float) * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&m->wb, (NH * 16 + 2 * NH * NH) * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&m->dsum, 64 * sizeof(float));
+    if (e != hipSuccess) {
+        delete m;
+        return set_err(c, SHG_ENOMEM, "shg_mlp_create: %s", hipGetErrorString(e));
+    }
+    m->m = m->p + NPARAM;
+    m->v = m->p + 2 * NPARAM;
+    m->g = m->p + 3 * NPARAM;
+    HIP_TRY(c, hipMemcpy(m->p, p.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemset(m->m, 0, 3 * NPARAM * sizeof(float)));
+    *out = m;
+    return 0;
+}
+
+extern "C" void shg_mlp_destroy(shg_mlp *m)
+{
+    if (!m) return;
+    (void)hipStreamSynchronize(m->ctx->stream);
+    (void)hipFree(m->p);
+    (void)hipFree(m->wb);
+    (void)hipFree(m->dsum);
+    (void)hipFree(m->tb.xh);
+    delete m;
+}
+
+extern "C" int shg_mlp_params(shg_mlp *m, float *host_out, const float *host_in)
+{
+    if (!m) return SHG_EINVAL;
+    shg_ctx *c = m->ctx;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (host_in) {
+        HIP_TRY(c, hipMemcpy(m->p, host_in, NPARAM * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemset(m->m, 0, 2 * NPARAM * sizeof(float)));
+        m->step = 0;
+    }
+    if (host_out) HIP_TRY(c, hipMemcpy(host_out, m->p, NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+    return 0;
+}
+
+extern "C" int shg_mlp_set_norm(shg_mlp *m, const float *mean, const float *std_, const float *lo, const float *hi)
+{
+    if (!m || !mean || !std_) return SHG_EINVAL;
+    for (int k = 0; k < NF; ++k) {
+        m->norm.mean[k] = mean[k];
+        m->norm.inv_std[k] = std_[k] > 0 ? 1.0f / std_[k] : 1.0f;
+        m->norm.lo[k] = lo ? lo[k] : -1e30f;
+        m->norm.hi[k] = hi ? hi[k] : 1e30f;
+    }
+    return 0;
+}
+
+extern "C" int shg_mlp_set_margin(shg_mlp *m, float margin)
+{
+    if (!m || !(margin >= 0)) return SHG_EINVAL;
+    m->margin = margin;
+    return 0;
+}
+
+static int ensure_tb(shg_mlp *m, int B)
+{
+    if (B <= m->tb_cap) return 0;
+    shg_ctx *c = m->ctx;
+    if (m->tb.xh) HIP_TRY(c, hipFree(m->tb.xh));
+    size_t per = 16 + 9 * NH + 2;
+    float *buf = nullptr;
+    HIP_TRY(c, hipMalloc((void **)&buf, (size_t)B * per * sizeof(float)));
+    m->tb.xh = buf;
+    m->tb.z = buf + (size_t)B * 16;
+    m->tb.act = m->tb.z + (size_t)B * 3 * NH;
+    m->tb.dl = m->tb.act + (size_t)B * 3 * NH;
+    m->tb.gy = m->tb.dl + (size_t)B * 3 * NH;
+    m->tb.loss = m->tb.gy + B;
+    m->tb_cap = B;
+    return 0;
+}
+
+// forward + backward on one batch; gradient left in the model (device)
+static int mlp_grad(shg_mlp *m, const float *X, const float *Y, int B, float q)
+{
+    shg_ctx *c = m->ctx;
+    int rc = ensure_tb(m, B);
+    if (rc) return rc;
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((B + 127) / 128), dim3(128), 0, s, B, X, Y, m->p, m->norm, q, m->tb);
+    hipLaunchKernelGGL(k_mlp_bwd, dim3((B + 127) / 128), dim3(128), 0, s, B, m->p, m->tb);
+    hipLaunchKernelGGL(k_mlp_grad, dim3((NPARAM + 255) / 256), dim3(256), 0, s, B, m->tb, m->g);
+    HIP_TRY(c, hipGetLastError());
+    return 0;
+}
+
+extern "C" int shg_mlp_grad(shg_mlp *m, const float *X, const float *Y, int B, float quantile, float *grad_out,
+                            float *loss_out)
+{
+    if (!m || !X || !Y || B < 1) return SHG_EINVAL;
+    int rc = mlp_grad(m, X, Y, B, quantile);
+    if (rc) return rc;
+    shg_ctx *c = m->ctx;
+    if (grad_out) HIP_TRY(c, hipMemcpyAsync(grad_out, m->g, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    if (loss_out) {
+        hipLaunchKernelGGL(k_sum_f32, dim3(1), dim3(256), 0, c->stream, B, m->tb.loss, loss_out);
+        HIP_TRY(c, hipGetLastError());
+    }
+    return 0;
+}
+
+extern "C" int shg_mlp_train_step(shg_mlp *m, const float *X, const float *Y, int B, float lr, float quantile,
+                                  float *loss_out)
+{
+    int rc = shg_mlp_grad(m, X, Y, B, quantile, nullptr, loss_out);
+    if (rc) return rc;
+    m->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    float c1 = 1.0f - powf(b1, (float)m->step), c2 = 1.0f - powf(b2, (float)m->step);
+    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->ctx->stream, m->p, m->m, m->v, m->g, lr,
+                       b1, b2, 1e-8f, c1, c2);
+    HIP_TRY(m->ctx, hipGetLastError());
+    return 0;
+}
+
+static int mlp_predict(shg_mlp *m, const float *feat, int64_t n, float *pred, int32_t *in_range)
+{
+    shg_ctx *c = m->ctx;
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k_mlp_pack, dim3((NH * 16 + 2 * NH * NH + 255) / 256), dim3(256), 0, s, m->p, m->wb);
+    if (n > 0) {
+        int64_t tiles = (n + 15) / 16;
+        unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 4096);
+        hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, s, n, feat, m->wb, m->p, m->norm, pred, in_range);
+    }
+    HIP_TRY(c, hipGetLastError());
+    return 0;
+}
+
+extern "C" int shg_mlp_predict(shg_mlp *m, const float *feat, int64_t n, float *pred, int32_t *in_range)
+{
+    if (!m || n < 0 || (n > 0 && (!feat || !pred || !in_range))) return SHG_EINVAL;
+    return mlp_predict(m, feat, n, pred, in_range);
+}
+
+extern "C" int shg_mlp_save(shg_mlp *m, const char *path)
+{
+    if (!m || !path) return SHG_EINVAL;
+    std::vector<float> p(NPARAM);
+    int rc = shg_mlp_params(m, p.data(), nullptr);
+    if (rc) return rc;
+    FILE *f = fopen(path, "wb");
+    if (!f) return set_err(m->ctx, SHG_EINVAL, "shg_mlp_save: cannot open %s", path);
+    const char magic[8] = {'S', 'H', 'G', 'M', 'L', 'P', '0', '1'};
+    fwrite(magic, 1, 8, f);
+    fwrite(p.data(), sizeof(float), NPARAM, f);
+    fwrite(&m->norm, sizeof(MlpNorm), 1, f);
+    fwrite(&m->margin, sizeof(float), 1, f);
+    fclose(f);
+    return 0;
+}
+
+extern "C" int shg_mlp_load(shg_mlp *m, const char *path)
+{
+    if (!m || !path) return SHG_EINVAL;
+    FILE *f = fopen(path, "rb");
+    if (!f) return set_err(m->ctx, SHG_EINVAL, "shg_mlp_load: cannot open %s", path);
+    char magic[8];
+    std::vector<float> p(NPARAM);
+    MlpNorm nm;
+    float margin;
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "SHGMLP01", 8) == 0 &&
+              fread(p.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM && fread(&nm, sizeof(nm), 1, f) == 1 &&
+              fread(&margin, sizeof(float), 1, f) == 1;
+    fclose(f);
+    if (!ok) return set_err(m->ctx, SHG_EINVAL, "shg_mlp_load: %s is not a model file", path);
+    int rc = shg_mlp_params(m, nullptr, p.data());
+    if (rc) return rc;
+    m->norm = nm;
+    m->margin = margin;
+    return 0;
+}
+
+// features and analytic bound of n pairs (device outputs: feat [n][12] fp32, logb [n] fp32)
+extern "C" int shg_screen_features(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
+                                   int64_t n, float *feat, float *logb)
+{
+    const char *what = "shg_screen_features";
+    if (!c) return SHG_EINVAL;
+    if ((int)op < 0 || (int)op > 4) return set_err(c, SHG_EINVAL, "%s: unknown operator", what);
+    if ((op == SHG_ERF || op == SHG_ERFC || op == SHG_GAUSS) && !(omega > 0.0))
+        return set_err(c, SHG_EINVAL, "%s: omega must be positive", what);
+    int rc = check_shells(c, sh, what);
+    if (rc) return rc;
+    if (n < 0) return set_err(c, SHG_EINVAL, "%s: n < 0", what);
+    if (n == 0) return 0;
+    if (!pairs || !feat || !logb) return set_err(c, SHG_EINVAL, "%s: NULL pointer", what);
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->err, 0, 1);
+    if ((rc = prep_shells(c, sh, LMAX, c->w, c->w_cap))) return rc;
+    if ((rc = grow(c, c->stats, c->stats_cap, (size_t)sh->nshell * STAT + 1))) return rc;
+    hipLaunchKernelGGL(k_shell_stats, dim3((sh->nshell + 255) / 256), dim3(256), 0, s, sh->nshell, sh->nprim,
+                       sh->prim_off, sh->exps, c->w, c->stats);
+    static const BoundTab bt = build_bound_table();
+    hipLaunchKernelGGL(k_bound_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pairs, sh->center,
+                       sh->l, c->stats, (int)op, omega, bt, feat, logb);
+    HIP_TRY(c, hipMemcpyAsync(c->host_rb, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return decode_err(c, c->host_rb[0], what);
+}
+
+extern "C" int shg_block_logmax(shg_ctx *c, const shg_shells *sh, const int32_t *pairs, int64_t n,
+                                const int64_t *out_off, const double *out, float *y)
+{
+    if (!c || !sh || n < 0) return SHG_EINVAL;
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_block_logmax, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, pairs, sh->l,
+                       out_off, out, y);
+    HIP_TRY(c, hipGetLastError());
+    return 0;
+}
+
+// keep[i] = 0 when the pair may be skipped: analytic bound below tau, or the
+// predictor (features inside its training range) plus its margin below tau
+__global__ void k_keep(int64_t n, const float *logb, const float *pred, const int32_t *in_range, float log_tau,
+                       float margin, int use_mlp, int32_t *keep)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int k = 1;
+    if (logb[i] < log_tau) k = 0;
+    else if (use_mlp && in_range[i] && pred[i] + margin < log_tau) k = 0;
+    keep[i] = k;
+}
+
+namespace shg {
+// screening decisions for a plan: keep flags (device int32 [n]); returns 0 or error
+int screen_pairs(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
+                 double tau, shg_mlp *mlp, int32_t *keep, float *work /* [n * 15] */)
+{
+    float *feat = work, *logb = work + (size_t)n * NF, *pred = logb + n;
+    int32_t *inr = (int32_t *)(pred + n);
+    int rc = shg_screen_features(c, sh, op, omega, pairs, n, feat, logb);
+    if (rc) return rc;
+    if (mlp) {
+        if (mlp->ctx != c) return set_err(c, SHG_EINVAL, "screen: model belongs to another context");
+        if ((rc = mlp_predict(mlp, feat, n, pred, inr))) return rc;
+    }
+    hipLaunchKernelGGL(k_keep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, logb, pred, inr,
+                       (float)log10(tau), mlp ? mlp->margin : 0.0f, mlp ? 1 : 0, keep);
+    HIP_TRY(c, hipGetLastError());
+    return 0;
+}
+}  // namespace shg

@@ -19,7 +19,11 @@ ERRORS = {-1: "SHG_EINVAL", -2: "SHG_ENOMEM", -3: "SHG_EDEVICE"}
 EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pairs_deriv", "shg_aab",
            "shg_set_tile_shape", "shg_get_tile_shape", "shg_autotune", "shg_tuning_save", "shg_tuning_load",
            "shg_profile_enable", "shg_profile_read", "shg_plan_create", "shg_plan_execute",
-           "shg_plan_autotune", "shg_plan_set_mode", "shg_plan_mode", "shg_plan_destroy")
+           "shg_plan_autotune", "shg_plan_set_mode", "shg_plan_mode", "shg_plan_destroy",
+           "shg_plan_stats", "shg_plan_kernel_ms", "shg_plan_skipped",
+           "shg_plan_create_screened", "shg_mlp_create", "shg_mlp_destroy", "shg_mlp_params", "shg_mlp_set_norm",
+           "shg_mlp_set_margin", "shg_mlp_train_step", "shg_mlp_grad", "shg_mlp_predict", "shg_mlp_save",
+           "shg_mlp_load", "shg_screen_features", "shg_block_logmax")
 
 
 class ShgShells(C.Structure):
@@ -75,6 +79,26 @@ def load_library(path: str = LIB_PATH):
     lib.shg_plan_mode.argtypes = [P]
     lib.shg_plan_destroy.argtypes = [P]
     lib.shg_plan_destroy.restype = None
+    lib.shg_plan_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.shg_plan_kernel_ms.argtypes = [P, I, C.POINTER(C.c_double)]
+    lib.shg_plan_skipped.argtypes = [P, P, C.c_int64]
+    lib.shg_plan_skipped.restype = C.c_int64
+    lib.shg_plan_create_screened.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, P, P, P,
+                                             C.c_uint, C.c_double, P, C.POINTER(C.c_void_p),
+                                             C.POINTER(C.c_int64)]
+    lib.shg_mlp_create.argtypes = [P, C.c_uint64, C.POINTER(C.c_void_p)]
+    lib.shg_mlp_destroy.argtypes = [P]
+    lib.shg_mlp_destroy.restype = None
+    lib.shg_mlp_params.argtypes = [P, P, P]
+    lib.shg_mlp_set_norm.argtypes = [P, P, P, P, P]
+    lib.shg_mlp_set_margin.argtypes = [P, C.c_float]
+    lib.shg_mlp_train_step.argtypes = [P, P, P, I, C.c_float, C.c_float, P]
+    lib.shg_mlp_grad.argtypes = [P, P, P, I, C.c_float, P, P]
+    lib.shg_mlp_predict.argtypes = [P, P, C.c_int64, P, P]
+    lib.shg_mlp_save.argtypes = [P, C.c_char_p]
+    lib.shg_mlp_load.argtypes = [P, C.c_char_p]
+    lib.shg_screen_features.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, P, P]
+    lib.shg_block_logmax.argtypes = [P, C.POINTER(ShgShells), P, C.c_int64, P, P, P]
     _lib = lib
     return lib
 
@@ -188,16 +212,27 @@ PLAN_NO_GRAPH = 2
 
 
 class Plan:
-    """A recorded evaluation (shg_plan_*): fixed shells, operator, pairs and outputs."""
+    """A recorded evaluation (shg_plan_*): fixed shells, operator, pairs and outputs.
+    With `tau` the plan is screened (shg_plan_create_screened): pairs whose analytic
+    bound, or (with `mlp`) learned prediction plus margin, is below tau are skipped."""
 
     def __init__(self, engine: "Engine", dsh: DeviceShells, op: str, omega: float, pairs, out_off, out, dout=None,
-                 flags: int = 0):
+                 flags: int = 0, tau: float | None = None, mlp: "Mlp | None" = None):
         self.engine = engine
-        self.keep = (dsh, pairs, out_off, out, dout)   # the plan references these buffers
+        self.keep = (dsh, pairs, out_off, out, dout, mlp)   # the plan references these buffers
         h = C.c_void_p()
-        engine._check(engine.lib.shg_plan_create(engine.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs),
-                                                 int(pairs.shape[0]), _ptr(out_off), _ptr(out), _ptr(dout),
-                                                 int(flags), C.byref(h)))
+        self.n_skipped = 0
+        if tau is None:
+            engine._check(engine.lib.shg_plan_create(engine.ctx, C.byref(dsh.c), OPS[op], float(omega),
+                                                     _ptr(pairs), int(pairs.shape[0]), _ptr(out_off), _ptr(out),
+                                                     _ptr(dout), int(flags), C.byref(h)))
+        else:
+            ns = C.c_int64()
+            engine._check(engine.lib.shg_plan_create_screened(
+                engine.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs), int(pairs.shape[0]),
+                _ptr(out_off), _ptr(out), _ptr(dout), int(flags), float(tau), mlp.h if mlp else None, C.byref(h),
+                C.byref(ns)))
+            self.n_skipped = ns.value
         self.h = h
 
     def execute(self):
@@ -210,6 +245,24 @@ class Plan:
 
     def set_mode(self, persistent: bool):
         self.engine._check(self.engine.lib.shg_plan_set_mode(self.h, int(persistent)))
+
+    def stats(self):
+        """(pairs evaluated, their algorithmic bytes)"""
+        k, b = C.c_int64(), C.c_int64()
+        self.engine._check(self.engine.lib.shg_plan_stats(self.h, C.byref(k), C.byref(b)))
+        return k.value, b.value
+
+    def skipped(self) -> np.ndarray:
+        n = self.engine.lib.shg_plan_skipped(self.h, None, 0)
+        ids = np.zeros(max(n, 0), np.int32)
+        if n > 0:
+            self.engine.lib.shg_plan_skipped(self.h, ids.ctypes.data_as(C.c_void_p), n)
+        return ids
+
+    def kernel_ms(self, reps=3) -> float:
+        ms = C.c_double()
+        self.engine._check(self.engine.lib.shg_plan_kernel_ms(self.h, reps, C.byref(ms)))
+        return ms.value
 
     @property
     def mode(self) -> str:
@@ -225,6 +278,86 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+NPARAM = 9217
+NFEAT = 12
+
+
+class Mlp:
+    """The learned prescreener (shg_mlp_*); device buffers are torch tensors."""
+
+    def __init__(self, engine: "Engine", seed: int = 0):
+        self.engine = engine
+        h = C.c_void_p()
+        engine._check(engine.lib.shg_mlp_create(engine.ctx, C.c_uint64(seed), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.engine.lib.shg_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(NPARAM, np.float32)
+        self.engine._check(self.engine.lib.shg_mlp_params(self.h, out.ctypes.data_as(C.c_void_p), None))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        self.engine._check(self.engine.lib.shg_mlp_params(self.h, None, p.ctypes.data_as(C.c_void_p)))
+
+    def set_norm(self, mean, std, lo=None, hi=None):
+        arrs = [np.ascontiguousarray(x, np.float32) if x is not None else None for x in (mean, std, lo, hi)]
+        ptrs = [a.ctypes.data_as(C.c_void_p) if a is not None else None for a in arrs]
+        self.engine._check(self.engine.lib.shg_mlp_set_norm(self.h, *ptrs))
+
+    def set_margin(self, m: float):
+        self.engine._check(self.engine.lib.shg_mlp_set_margin(self.h, float(m)))
+
+    def train_step(self, X, y, lr, quantile, loss_out=None):
+        self.engine._check(self.engine.lib.shg_mlp_train_step(self.h, _ptr(X), _ptr(y), int(X.shape[0]), float(lr),
+                                                              float(quantile), _ptr(loss_out)))
+
+    def grad(self, X, y, quantile, grad_out, loss_out=None):
+        self.engine._check(self.engine.lib.shg_mlp_grad(self.h, _ptr(X), _ptr(y), int(X.shape[0]), float(quantile),
+                                                        _ptr(grad_out), _ptr(loss_out)))
+
+    def predict(self, X, pred, in_range):
+        self.engine._check(self.engine.lib.shg_mlp_predict(self.h, _ptr(X), int(X.shape[0]), _ptr(pred),
+                                                           _ptr(in_range)))
+
+    def save(self, path):
+        self.engine._check(self.engine.lib.shg_mlp_save(self.h, path.encode()))
+
+    def load(self, path):
+        self.engine._check(self.engine.lib.shg_mlp_load(self.h, path.encode()))
+
+
+def screen_features(engine: Engine, dsh: DeviceShells, op: str, omega: float, pairs):
+    """(features [n,12] fp32, log10 analytic bound [n] fp32) on the device."""
+    torch = engine.torch
+    n = int(pairs.shape[0])
+    feat = torch.empty((max(n, 1), NFEAT), dtype=torch.float32, device=pairs.device)
+    logb = torch.empty(max(n, 1), dtype=torch.float32, device=pairs.device)
+    engine._check(engine.lib.shg_screen_features(engine.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs), n,
+                                                 _ptr(feat), _ptr(logb)))
+    return feat[:n], logb[:n]
+
+
+def block_logmax(engine: Engine, dsh: DeviceShells, pairs, out_off, out):
+    torch = engine.torch
+    n = int(pairs.shape[0])
+    y = torch.empty(max(n, 1), dtype=torch.float32, device=pairs.device)
+    engine._check(engine.lib.shg_block_logmax(engine.ctx, C.byref(dsh.c), _ptr(pairs), n, _ptr(out_off), _ptr(out),
+                                              _ptr(y)))
+    return y[:n]
 
 
 def run_workload_pairs(engine: Engine, w, op: str, deriv: bool):

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "shg.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(shg_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:int64_t|int|void|const char \*)\s*\*?\s*(shg_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 

@@ -1,0 +1,123 @@
+"""Prescreening on the GPU: the analytic bound dominates every block; the
+network's forward (bf16 MFMA) and gradients (library kernels) match the FP64
+reference on identical bf16-rounded weights; training lowers the loss; screened
+plans keep exact blocks and zero the skipped ones."""
+import numpy as np
+import pytest
+
+import mlp_reference as mr
+from paper_1701_06588_amd import inputs
+
+pytestmark = pytest.mark.gpu
+OPS = ("overlap", "coulomb", "erf", "erfc", "gauss")
+
+
+@pytest.fixture(scope="module")
+def engine():
+    from paper_1701_06588_amd import shg
+    e = shg.Engine()
+    yield e
+    e.close()
+
+
+def _dev(w):
+    import torch
+    dev = torch.device("cuda")
+    off, tot = w.out_offsets()
+    return (torch.as_tensor(np.ascontiguousarray(w.pairs, np.int32), device=dev), torch.as_tensor(off, device=dev),
+            torch.empty(max(tot, 1), dtype=torch.float64, device=dev))
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_analytic_bound_dominates(engine, op):
+    import torch
+    from paper_1701_06588_amd import shg
+    for w in (inputs.small_pairs(91, 4000, dmax=12.0), inputs.screen5000(n_atoms=800, box=25.0)):
+        print(f"case bound {w.name} op={op} n={len(w.pairs)}", flush=True)
+        pairs, oo, out = _dev(w)
+        dsh = engine.shells(w.shells)
+        engine.pairs(dsh, op, w.omega[op], pairs, oo, out)
+        _, logb = shg.screen_features(engine, dsh, op, w.omega[op], pairs)
+        y = shg.block_logmax(engine, dsh, pairs, oo, out)
+        torch.cuda.synchronize()
+        yb, lb = y.cpu().numpy(), logb.cpu().numpy()
+        real = yb > -29.9                       # blocks that are not exactly zero
+        slack = lb[real] - yb[real]
+        assert slack.min() >= -1e-6, (op, w.name, slack.min())
+
+
+def test_mlp_forward_and_gradient_match_reference(engine):
+    import torch
+    from paper_1701_06588_amd import shg
+    rng = np.random.default_rng(5)
+    B = 512
+    X = rng.normal(size=(B, 12)).astype(np.float32) * 2 + 1
+    y = (rng.normal(size=B) * 4 - 8).astype(np.float32)
+    mean = X.mean(0).astype(np.float32)
+    std = X.std(0).astype(np.float32)
+    mlp = shg.Mlp(engine, 3)
+    mlp.set_norm(mean, std)
+    p = mlp.params().astype(np.float64)
+    dX = torch.as_tensor(X, device="cuda")
+    dy = torch.as_tensor(y, device="cuda")
+    grad = torch.empty(9217, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    mlp.grad(dX, dy, 0.95, grad, loss)
+    pred = torch.empty(B, dtype=torch.float32, device="cuda")
+    inr = torch.empty(B, dtype=torch.int32, device="cuda")
+    mlp.predict(dX, pred, inr)
+    torch.cuda.synchronize()
+    L, g, yp = mr.loss_and_grad(p, X, y, mean, std, 0.95, rounding=True)
+    assert abs(loss.item() / B - L) <= 1e-4 * abs(L)
+    gg = grad.cpu().numpy().astype(np.float64)
+    off = 0
+    for name, shp in mr.SIZES:
+        n = int(np.prod(shp))
+        a, b = gg[off:off + n], g[off:off + n]
+        assert np.linalg.norm(a - b) <= 2e-4 * np.linalg.norm(b) + 1e-9, (name, np.linalg.norm(a - b), np.linalg.norm(b))
+        off += n
+    pr = pred.cpu().numpy().astype(np.float64)
+    # MFMA inference sums in a different order: compare within bf16-level noise
+    assert np.max(np.abs(pr - yp)) <= 2e-2 * (1 + np.max(np.abs(yp))), np.max(np.abs(pr - yp))
+    assert inr.cpu().numpy().all()
+    mlp.close()
+
+
+def test_training_lowers_loss(engine):
+    import torch
+    from paper_1701_06588_amd import screen
+    w = inputs.screen5000(n_atoms=600, box=22.0)
+    X, y, held = screen.collect(engine, w)
+    mlp, stats = screen.train(engine, X, y, held, epochs=6, batch=2048, log=lambda m: None)
+    assert stats["held_mae"] < 3.0, stats
+    mlp.close()
+
+
+@pytest.mark.parametrize("op", ["overlap", "erfc"])
+def test_screened_plan(engine, op):
+    import torch
+    from paper_1701_06588_amd import shg
+    w = inputs.screen5000(n_atoms=900, box=26.0)
+    print(f"case screened plan op={op} n={len(w.pairs)}", flush=True)
+    pairs, oo, out = _dev(w)
+    dsh = engine.shells(w.shells)
+    ref = torch.empty_like(out)
+    engine.pairs(dsh, op, w.omega[op], pairs, oo, ref)
+    tau = 1e-12
+    plan = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, None, shg.PLAN_PERSISTENT, tau=tau)
+    out.fill_(float("nan"))
+    # skipped blocks were zeroed at creation; executions touch kept blocks only
+    plan2 = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, None, shg.PLAN_PERSISTENT, tau=tau)
+    plan2.execute()
+    torch.cuda.synchronize()
+    got, r = out.cpu().numpy(), ref.cpu().numpy()
+    off, _ = w.out_offsets()
+    sz = w.block_sizes()
+    zero = np.abs(got) == 0
+    keep_equal = (got == r) | zero
+    assert keep_equal.all()
+    # every zeroed element is tiny in the exact result (bound-only screening is rigorous)
+    assert np.all(np.abs(r[zero]) <= tau)
+    assert plan2.n_skipped > 0 or op == "erfc"
+    plan.close()
+    plan2.close()
