@@ -6,13 +6,28 @@ within 12 bohr (1.61e6 shell pairs), evaluated for all five operators (overlap,
 Coulomb, erfc(0.11 r)/r, erf(0.33 r)/r, exp(-r^2)) with values and d/dR_a.
 Inputs are synthetic (seeded) and resident in HBM before the timed region.
 
-Prints ONE JSON line (rank 0). Fields beyond the common contract:
-  roofline      dominant kernel (largest share of the step) measured live with
-                HIP events on the library stream; algorithmic bytes per launch
-                = pairs of the launch x (8 (2la+1)(2lb+1) 4 + 16) (see workmodel.py)
+Three paths over the same pair lists, each timed with HIP events on the
+library stream over --steps steps after --warmup untimed ones:
+  plain             shg_pairs_deriv per operator (binning + one launch per class)
+  batched           one recorded plan per operator (binned once, hipGraph replay,
+                    persistent or per-class launch chosen by the plan autotuner)
+  batched+screened  the same with screening: pairs whose analytic bound (covering
+                    values and d/dR_a) is below tau_blk = 1e-10 / N_candidates are
+                    skipped (blocks zeroed once when the plan is made)
+`value` is the batched+screened rate in candidate blocks per second (every
+block of the step counts, skipped or not). Kept blocks are checked bitwise
+against the plain path; the missed mass is exact (L1 of the plain path's values
+and derivatives over every skipped block).
+
+Prints ONE JSON line. Fields beyond the common contract:
+  roofline      dominant kernel of the value path, measured live with HIP events
+                on the library stream: algorithmic bytes (and flops) per launch
+                from workmodel.py over the pairs the launch evaluates
   cpu_baseline  the CPU oracle on a bounded sample of the same pairs
-  paths         blocks/s of each evaluated path (plain per-class launches, and the
-                batched/graph path when available)
+  paths         blocks/s and ms per step of each path
+  screening     skipped pairs and missed mass of the value path
+  ablation      the 5000-atom screening workload (Coulomb and erfc, values):
+                no screening vs analytic bound vs bound + trained network
 """
 from __future__ import annotations
 
@@ -25,8 +40,53 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
-FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, published
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed(eng, fn, steps, warmup):
+    """average ms per call of fn over `steps` calls, HIP events on the library stream"""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(eng.stream)
+    wall0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    t1.record(eng.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    return t0.elapsed_time(t1) / steps, wall
+
+
+def roofline_of(kernel, ms, nbytes, flops, launches):
+    """roofline entry for `launches` launches of one kernel taking `ms` on average"""
+    b = nbytes / launches
+    f = flops / launches
+    t_hbm = b / (HBM_PEAK_GBS * 1e9)
+    t_alu = f / (FP64_PEAK_TFLOPS * 1e12)
+    s = ms / 1e3
+    gbs = b / s / 1e9
+    tfl = f / s / 1e12
+    if t_alu > t_hbm:
+        r = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+             "frac": round(tfl / FP64_PEAK_TFLOPS, 4)}
+    else:
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    r.update({"traffic": None, "kernel": kernel, "avg_launch_ms": round(ms, 4),
+              "alg_bytes_per_launch": int(b), "alg_flops_per_launch": int(f),
+              "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+              "fp64_tflops": round(tfl, 3), "fp64_frac": round(tfl / FP64_PEAK_TFLOPS, 4),
+              "roof_frac": round(max(t_hbm, t_alu) / s, 4)})
+    return r
 
 
 def main():
@@ -37,6 +97,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=300000,
                     help="pairs per operator timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="skip loading the tuned tile shapes")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the screening ablation")
+    ap.add_argument("--paths", default="plain,batched,screened",
+                    help="comma list of paths to run (the value needs 'screened')")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -48,6 +111,7 @@ def main():
     import torch
     from paper_1701_06588_amd import inputs, shg, workmodel
 
+    paths = set(args.paths.split(","))
     w = inputs.five_ops500()
     eng = shg.Engine()
     if not args.no_tune:
@@ -59,60 +123,152 @@ def main():
     pairs = torch.as_tensor(np.ascontiguousarray(w.pairs, np.int32), device=dev)
     out_off = torch.as_tensor(off, device=dev)
     ops = list(inputs.FIVE_OPS)
+    n = len(w.pairs)
+    blocks_per_step = n * len(ops)
     outs = {op: torch.empty(tot, dtype=torch.float64, device=dev) for op in ops}
     douts = {op: torch.empty(3 * tot, dtype=torch.float64, device=dev) for op in ops}
-    n = len(w.pairs)
+    res_paths = {}
 
-    def step():
+    # ---- plain per-class launches ----
+    def step_plain():
         for op in ops:
             eng.pairs(dsh, op, w.omega[op], pairs, out_off, outs[op], douts[op])
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(eng.stream)
-    wall0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    t1.record(eng.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1) / args.steps
-    blocks_per_step = n * len(ops)
-    value = blocks_per_step / (ms / 1e3)
+    log("plain path")
+    ms_plain, wall_plain = timed(eng, step_plain, args.steps, args.warmup)
+    res_paths["plain"] = {"blocks_per_s": round(blocks_per_step / (ms_plain / 1e3), 1), "ms_per_step": round(ms_plain, 4)}
 
-    # ---- roofline of the dominant kernel (one extra profiled step, untimed) ----
-    eng.profile_enable(True)
-    step()
+    # ---- batched: one plan per operator (writes the same outputs as plain) ----
+    if "batched" in paths:
+        log("batched path")
+        bplans = [shg.Plan(eng, dsh, op, w.omega[op], pairs, out_off, outs[op], douts[op]) for op in ops]
+        modes = []
+        for p in bplans:
+            p.autotune(3)
+            modes.append(p.mode)
+        ms_b, _ = timed(eng, lambda: [p.execute() for p in bplans], args.steps, args.warmup)
+        res_paths["batched"] = {"blocks_per_s": round(blocks_per_step / (ms_b / 1e3), 1), "ms_per_step": round(ms_b, 4),
+                                "modes": dict(zip(ops, modes))}
+        for p in bplans:
+            p.close()
+        step_plain()            # plain outputs back in place (identical anyway)
     torch.cuda.synchronize()
-    best = None
-    total_ms = 0.0
-    for la in range(5):
-        for lb in range(5):
-            kms, nl, npairs = eng.profile_read(la, lb, True)
-            total_ms += kms
-            if nl and (best is None or kms > best[0]):
-                best = (kms, nl, npairs, la, lb)
-    bin_ms, bin_calls, _ = eng.profile_read(-1, 0, 0)
-    eng.profile_enable(False)
-    kms, nl, npairs, la, lb = best
-    bytes_per_launch = float(workmodel.pair_bytes(la, lb, True)) * npairs / nl
-    avg_ms = kms / nl
-    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_tile<{la}, {lb}, true>", "avg_launch_ms": round(avg_ms, 4),
-                "alg_bytes_per_launch": int(bytes_per_launch),
-                "step_share": round(kms / (total_ms + bin_ms), 3),
-                "step_hbm_frac": round(workmodel.workload_bytes(w, True) * len(ops) / (ms / 1e3) / 1e9
-                                       / HBM_PEAK_GBS, 4)}
+
+    # ---- batched + screened (the value path) ----
+    tau = 1e-10 / blocks_per_step
+    souts = {op: torch.empty(tot, dtype=torch.float64, device=dev) for op in ops}
+    sdouts = {op: torch.empty(3 * tot, dtype=torch.float64, device=dev) for op in ops}
+    log("batched+screened path")
+    splans = [shg.Plan(eng, dsh, op, w.omega[op], pairs, out_off, souts[op], sdouts[op], tau=tau) for op in ops]
+    for p in splans:
+        p.autotune(3)
+    ms_s, wall_s = timed(eng, lambda: [p.execute() for p in splans], args.steps, args.warmup)
+    value = blocks_per_step / (ms_s / 1e3)
+    res_paths["batched+screened"] = {"blocks_per_s": round(value, 1), "ms_per_step": round(ms_s, 4),
+                                     "modes": {op: p.mode for op, p in zip(ops, splans)}}
+
+    # ---- kept blocks bitwise equal to plain; exact missed mass over skipped blocks ----
+    screening = {"tau_blk": tau, "rule": "analytic bound over values and d/dR_a < tau_blk", "per_op": {}}
+    bad = 0
+    m_tot = dm_tot = 0.0
+    for op, p in zip(ops, splans):
+        for s_, r_ in ((souts[op], outs[op]), (sdouts[op], douts[op])):
+            bad += int(((s_ != r_) & (s_ != 0)).sum().item())
+        mv = float(outs[op][souts[op] == 0].abs().sum().item())
+        md = float(douts[op][sdouts[op] == 0].abs().sum().item())
+        m_tot += mv
+        dm_tot += md
+        screening["per_op"][op] = {"skipped": int(p.n_skipped), "missed_mass": mv, "missed_mass_deriv": md}
+    screening.update({"skipped": int(sum(p.n_skipped for p in splans)), "candidates": blocks_per_step,
+                      "missed_mass": m_tot, "missed_mass_deriv": dm_tot, "kept_blocks_bitwise_equal": bad == 0,
+                      "audit": "every skipped block evaluated exactly (plain path), L1 of its elements"})
+
+    # ---- roofline of the dominant kernel of the value path ----
+    per = []
+    skip_mask = {}
+    for op, p in zip(ops, splans):
+        kept, nbytes = p.stats()
+        mask = np.ones(n, bool)
+        mask[p.skipped()] = False
+        skip_mask[op] = mask
+        flops = workmodel.workload_flops(w, op, True, mask)
+        kms = p.kernel_ms(5)
+        name = "shg::k_persist<true>" if p.mode == "persistent" else f"per-class k_tile<la, lb, true> ({op})"
+        per.append((name, kms, nbytes, flops, op))
+    groups = {}
+    for name, kms, nbytes, flops, op in per:
+        g = groups.setdefault(name, [0.0, 0, 0, 0, []])
+        g[0] += kms
+        g[1] += nbytes
+        g[2] += flops
+        g[3] += 1
+        g[4].append(op)
+    name, (kms_sum, nbytes, flops, nl, gops) = max(groups.items(), key=lambda kv: kv[1][0])
+    roofline = roofline_of(name, kms_sum / nl, nbytes, flops, nl)
+    roofline["launches_averaged"] = {"ops": gops, "per_op_ms": {op: round(k, 4) for _, k, _, _, op in per}}
+    roofline["step_share"] = round(kms_sum / ms_s, 3)
+
+    for p in splans:
+        p.close()
+    del souts, sdouts
+    torch.cuda.synchronize()
+
+    # ---- screening ablation on the 5000-atom workload (Coulomb, erfc; values) ----
+    ablation = None
+    if not args.no_ablation:
+        from paper_1701_06588_amd import screen
+        log("ablation")
+        w5 = inputs.screen5000()
+        n5 = len(w5.pairs)
+        off5, tot5 = w5.out_offsets()
+        dsh5 = eng.shells(w5.shells)
+        pairs5 = torch.as_tensor(np.ascontiguousarray(w5.pairs, np.int32), device=dev)
+        oo5 = torch.as_tensor(off5, device=dev)
+        ref5 = torch.empty(tot5, dtype=torch.float64, device=dev)
+        got5 = torch.empty(tot5, dtype=torch.float64, device=dev)
+        mlp = shg.Mlp(eng, 0)
+        mlp.load(screen.MODEL)
+        ops5 = list(w5.ops)
+        ncand = n5 * len(ops5)
+        ablation = {"workload": "screen5000: 5000 atoms, 60 bohr cube, basis as the 500-atom workload, "
+                                "ordered atom pairs within 12 bohr, values only",
+                    "pairs": n5, "candidates": ncand, "variants": {}}
+        steps5 = max(3, args.steps // 2)
+        for op in ops5:
+            ms_pl, _ = timed(eng, lambda: eng.pairs(dsh5, op, w5.omega[op], pairs5, oo5, ref5), steps5, 1)
+            ablation["variants"].setdefault("plain", {})[op] = {"ms": round(ms_pl, 4)}
+            torch.cuda.synchronize()
+            for tname, tau5 in (("tau_total", 1e-10 / ncand), ("tau_block", 1e-10)):
+                for vname, model, tt in (("batched", None, None), ("bound", None, tau5),
+                                         ("bound+mlp", mlp, tau5)):
+                    if vname == "batched" and tname == "tau_block":
+                        continue
+                    key = vname if vname == "batched" else f"{vname}@{tname}"
+                    log(f"ablation {op} {key}")
+                    p = shg.Plan(eng, dsh5, op, w5.omega[op], pairs5, oo5, got5, None, tau=tt, mlp=model)
+                    p.autotune(2)
+                    ms_v, _ = timed(eng, p.execute, steps5, 1)
+                    entry = {"ms": round(ms_v, 4), "skipped": int(p.n_skipped)}
+                    if tt is not None:
+                        entry["missed_mass"] = float(ref5[got5 == 0].abs().sum().item())
+                        entry["kept_bitwise_equal"] = bool(((got5 != ref5) & (got5 != 0)).sum().item() == 0)
+                    ablation["variants"].setdefault(key, {})[op] = entry
+                    p.close()
+        for key, d in ablation["variants"].items():
+            ms_sum = sum(v["ms"] for v in d.values())
+            d["blocks_per_s"] = round(ncand / (ms_sum / 1e3), 1)
+            if all("missed_mass" in v for k, v in d.items() if k in ops5):
+                d["missed_mass_total"] = sum(d[o]["missed_mass"] for o in ops5)
+        ablation["tau_total"] = 1e-10 / ncand
+        mlp.close()
+        del ref5, got5
+        torch.cuda.synchronize()
 
     # ---- CPU oracle on a bounded sample of the same pairs ----
     cpu = None
     if args.cpu_sample > 0:
         import oracle
+        log("cpu baseline")
         rng = np.random.default_rng(0)
         idx = np.sort(rng.choice(n, min(args.cpu_sample, n), replace=False))
         c0 = time.perf_counter()
@@ -131,7 +287,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": round(ms_s, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -139,14 +295,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "five_ops500: 500 atoms, 20 bohr cube, 4 shells/atom l 0..4 K 1..7, "
                                "ordered atom pairs within 12 bohr",
-                   "pairs": n, "operators": ops, "derivatives": True, "path": "plain per-class launches",
+                   "pairs": n, "operators": ops, "derivatives": True, "path": "batched+screened",
                    "blocks_per_step": blocks_per_step},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "wall_s_timed": round(wall, 3),
-        "binning_ms_per_call": round(bin_ms / max(bin_calls, 1), 4),
+        "paths": res_paths,
+        "speedup_vs_plain": round(ms_plain / ms_s, 3),
+        "screening": screening,
+        "ablation": ablation,
+        "wall_s_timed": round(wall_s, 3),
     }
-    print(json.dumps(res))
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -182,9 +182,11 @@ int  shg_mlp_load(shg_mlp *mlp, const char *path);
 /* The 12 screening features of each pair (device fp32 [n][12]: la, lb,
  * log10 alpha_min/max of a and of b, R, log10(1 + rho_min R^2), log10 bound,
  * erfc flag, omega R, log10(sum|w_a| sum|w_b|)) and log10 of the conservative
- * analytic bound on max|block| (device fp32 [n]). */
+ * analytic bound on max|block| (device fp32 [n]); with deriv != 0 the bound
+ * covers the d/dR_a elements too (the feature stays the value bound). */
 int  shg_screen_features(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
-                         const int32_t *pairs, int64_t n, float *feat, float *log10_bound);
+                         const int32_t *pairs, int64_t n, int deriv, float *feat,
+                         float *log10_bound);
 /* log10 max|block| (clamped at -30) of evaluated blocks (training targets) */
 int  shg_block_logmax(shg_ctx *ctx, const shg_shells *sh, const int32_t *pairs, int64_t n,
                       const int64_t *out_off, const double *out, float *y);
@@ -192,6 +194,9 @@ int  shg_block_logmax(shg_ctx *ctx, const shg_shells *sh, const int32_t *pairs, 
  * below tau, or (mlp non-NULL, features in range) whose prediction plus the
  * model margin is below log10(tau), is skipped: its block is set to zero once
  * here and never evaluated again; executions evaluate the kept pairs only.
+ * With dout the bound covers the d/dR_a elements as well and the model is not
+ * consulted (it predicts value magnitudes); it is consulted for SHG_COULOMB
+ * and SHG_ERFC only, the operators it is trained on.
  * *n_skipped (host, nullable) receives the number of skipped pairs. */
 int  shg_plan_create_screened(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
                               const int32_t *pairs, int64_t n, const int64_t *out_off,

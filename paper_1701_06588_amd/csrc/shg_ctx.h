@@ -105,9 +105,10 @@ __global__ void k_prep_shells(int nshell, const int32_t *l, const int32_t *nprim
                               int32_t *err);
 __global__ void k_scan_bins(const int32_t *hist, int nb, int32_t *starts, int32_t *cursor);
 __global__ void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor, int32_t *order);
-// screening decisions (shg_screen.hip): keep[i] = 0 if pair i may be skipped;
-// work: n * 15 floats of scratch
+// screening decisions (shg_screen.hip): keep[i] = 0 if pair i may be skipped
+// (with deriv the bound also covers the d/dR_a elements and the model is not
+// consulted); work: n * 15 floats of scratch
 int screen_pairs(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
-                 double tau, shg_mlp *mlp, int32_t *keep, float *work);
+                 int deriv, double tau, shg_mlp *mlp, int32_t *keep, float *work);
 
 }  // namespace shg

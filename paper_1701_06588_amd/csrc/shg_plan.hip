@@ -222,7 +222,7 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
             (void)hipFree(keep);
             return fail(set_err(c, SHG_ENOMEM, "shg_plan_create_screened: out of device memory"));
         }
-        rc = screen_pairs(c, sh, op, omega, pairs, n, tau, mlp, keep, work);
+        rc = screen_pairs(c, sh, op, omega, pairs, n, p->deriv, tau, mlp, keep, work);
         std::vector<int32_t> hkeep(n), horder(n);
         if (!rc && (hipMemcpy(hkeep.data(), keep, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
                     hipMemcpy(horder.data(), p->order, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess))

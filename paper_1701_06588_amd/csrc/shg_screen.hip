@@ -87,7 +87,8 @@ __device__ __forceinline__ double dfact_d(int n) { double f = 1; for (int i = n;
 
 // log10 of the analytic bound and the 12 features of one pair
 __global__ void k_bound_features(int64_t n, const int32_t *pairs, const double *center, const int32_t *l,
-                                 const double *st, int op, double omega, BoundTab bt, float *feat, float *logb)
+                                 const double *st, int op, double omega, int deriv, BoundTab bt, float *feat,
+                                 float *logb)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -99,10 +100,8 @@ __global__ void k_bound_features(int64_t n, const int32_t *pairs, const double *
     const double *sa = st + (size_t)a * STAT, *sb = st + (size_t)b * STAT;
     const double rmin = sa[0] * sb[0] / (sa[0] + sb[0]);
     const double PI_ = 3.141592653589793238462643383279502884;
-    double bound = 0.0;
-    const int jm = la < lb ? la : lb;
-    for (int j = 0; j <= jm; ++j) {
-        const int k = la + lb - j, pw = la + lb - 2 * j;
+    // bound on |O^(k)| (k-th R^2-derivative of the contracted radial term)
+    auto obound = [&](int k) {
         double ob;
         if (op == OP_OVERLAP || op == OP_GAUSS) {
             ob = pow(2.0, -1.5 - k) * sa[4 + KB + k] * sb[4 + KB + k];
@@ -115,10 +114,28 @@ __global__ void k_bound_features(int64_t n, const int32_t *pairs, const double *
                                 : 1e300;
             ob = fmin(nearb, farb) * (op == OP_ERFC ? 2.0 : 1.0);
         }
-        bound += ob * bt.cq[la][lb][j] * (pw == 0 ? 1.0 : pow(R, (double)pw));
+        return ob;
+    };
+    double bound = 0.0, dbound = 0.0;
+    const int jm = la < lb ? la : lb;
+    for (int j = 0; j <= jm; ++j) {
+        const int k = la + lb - j, pw = la + lb - 2 * j;
+        const double ok = obound(k);
+        bound += ok * bt.cq[la][lb][j] * (pw == 0 ? 1.0 : pow(R, (double)pw));
+        if (deriv) {
+            // d/dX_i [O^(k)(R^2) P_j(X)] = 2 X_i O^(k+1) P_j + O^(k) d_i P_j, with P_j homogeneous of
+            // degree pw and |P_j| <= Cq R^pw; on the sphere Bernstein's inequality gives
+            // |grad_tangential P_j| <= pw Cq, the radial part is pw P_j / R, so |d_i P_j| <= sqrt(2) pw Cq R^(pw-1)
+            double t = obound(k + 1) * 2.0 * R * (pw == 0 ? 1.0 : pow(R, (double)pw));
+            if (pw > 0) t += ok * 1.4142135623730951 * pw * (pw == 1 ? 1.0 : pow(R, (double)(pw - 1)));
+            dbound += t * bt.cq[la][lb][j];
+        }
     }
+    const double vbound = bound;
+    if (deriv) bound = fmax(bound, dbound);
     const double lb10 = bound > 0 ? log10(bound) : -300.0;
     logb[i] = (float)fmax(lb10, -300.0);
+    const double lv10 = vbound > 0 ? log10(vbound) : -300.0;
     float *f = feat + i * NF;
     f[0] = (float)la;
     f[1] = (float)lb;
@@ -128,7 +145,7 @@ __global__ void k_bound_features(int64_t n, const int32_t *pairs, const double *
     f[5] = (float)log10(sb[1]);
     f[6] = (float)R;
     f[7] = (float)log10(1.0 + rmin * R2);
-    f[8] = (float)fmax(lb10, -40.0);
+    f[8] = (float)fmax(lv10, -40.0);
     f[9] = op == OP_ERFC ? 1.0f : 0.0f;
     f[10] = (op == OP_ERF || op == OP_ERFC) ? (float)(omega * R) : 0.0f;
     f[11] = (float)log10(sa[2] * sb[2]);
@@ -711,7 +728,7 @@ extern "C" int shg_mlp_load(shg_mlp *m, const char *path)
 
 // features and analytic bound of n pairs (device outputs: feat [n][12] fp32, logb [n] fp32)
 extern "C" int shg_screen_features(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
-                                   int64_t n, float *feat, float *logb)
+                                   int64_t n, int deriv, float *feat, float *logb)
 {
     const char *what = "shg_screen_features";
     if (!c) return SHG_EINVAL;
@@ -731,7 +748,7 @@ extern "C" int shg_screen_features(shg_ctx *c, const shg_shells *sh, shg_op op, 
                        sh->prim_off, sh->exps, c->w, c->stats);
     static const BoundTab bt = build_bound_table();
     hipLaunchKernelGGL(k_bound_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pairs, sh->center,
-                       sh->l, c->stats, (int)op, omega, bt, feat, logb);
+                       sh->l, c->stats, (int)op, omega, deriv ? 1 : 0, bt, feat, logb);
     HIP_TRY(c, hipMemcpyAsync(c->host_rb, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     return decode_err(c, c->host_rb[0], what);
@@ -764,12 +781,14 @@ __global__ void k_keep(int64_t n, const float *logb, const float *pred, const in
 namespace shg {
 // screening decisions for a plan: keep flags (device int32 [n]); returns 0 or error
 int screen_pairs(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
-                 double tau, shg_mlp *mlp, int32_t *keep, float *work /* [n * 15] */)
+                 int deriv, double tau, shg_mlp *mlp, int32_t *keep, float *work /* [n * 15] */)
 {
     float *feat = work, *logb = work + (size_t)n * NF, *pred = logb + n;
     int32_t *inr = (int32_t *)(pred + n);
-    int rc = shg_screen_features(c, sh, op, omega, pairs, n, feat, logb);
+    int rc = shg_screen_features(c, sh, op, omega, pairs, n, deriv, feat, logb);
     if (rc) return rc;
+    // the model predicts value magnitudes of the operators it was trained on
+    if (deriv || (op != SHG_COULOMB && op != SHG_ERFC)) mlp = nullptr;
     if (mlp) {
         if (mlp->ctx != c) return set_err(c, SHG_EINVAL, "screen: model belongs to another context");
         if ((rc = mlp_predict(mlp, feat, n, pred, inr))) return rc;

@@ -97,7 +97,7 @@ def load_library(path: str = LIB_PATH):
     lib.shg_mlp_predict.argtypes = [P, P, C.c_int64, P, P]
     lib.shg_mlp_save.argtypes = [P, C.c_char_p]
     lib.shg_mlp_load.argtypes = [P, C.c_char_p]
-    lib.shg_screen_features.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, P, P]
+    lib.shg_screen_features.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, I, P, P]
     lib.shg_block_logmax.argtypes = [P, C.POINTER(ShgShells), P, C.c_int64, P, P, P]
     _lib = lib
     return lib
@@ -340,14 +340,15 @@ class Mlp:
         self.engine._check(self.engine.lib.shg_mlp_load(self.h, path.encode()))
 
 
-def screen_features(engine: Engine, dsh: DeviceShells, op: str, omega: float, pairs):
-    """(features [n,12] fp32, log10 analytic bound [n] fp32) on the device."""
+def screen_features(engine: Engine, dsh: DeviceShells, op: str, omega: float, pairs, deriv: bool = False):
+    """(features [n,12] fp32, log10 analytic bound [n] fp32) on the device; with
+    `deriv` the bound also covers the d/dR_a elements."""
     torch = engine.torch
     n = int(pairs.shape[0])
     feat = torch.empty((max(n, 1), NFEAT), dtype=torch.float32, device=pairs.device)
     logb = torch.empty(max(n, 1), dtype=torch.float32, device=pairs.device)
     engine._check(engine.lib.shg_screen_features(engine.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs), n,
-                                                 _ptr(feat), _ptr(logb)))
+                                                 int(deriv), _ptr(feat), _ptr(logb)))
     return feat[:n], logb[:n]
 
 

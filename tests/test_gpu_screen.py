@@ -46,6 +46,39 @@ def test_analytic_bound_dominates(engine, op):
         assert slack.min() >= -1e-6, (op, w.name, slack.min())
 
 
+def _block_absmax(x, starts, sizes):
+    """max |x| over each block [start, start + size) (blocks contiguous and in order)."""
+    m = np.maximum.reduceat(np.abs(x), starts)
+    m[sizes == 0] = 0.0
+    return m
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_derivative_bound_dominates(engine, op):
+    import torch
+    from paper_1701_06588_amd import shg
+    for w in (inputs.small_pairs(92, 3000, dmax=12.0), inputs.screen5000(n_atoms=500, box=21.0)):
+        print(f"case deriv bound {w.name} op={op} n={len(w.pairs)}", flush=True)
+        pairs, oo, out = _dev(w)
+        dout = torch.empty(3 * out.numel(), dtype=torch.float64, device=out.device)
+        dsh = engine.shells(w.shells)
+        engine.pairs(dsh, op, w.omega[op], pairs, oo, out, dout)
+        _, logb = shg.screen_features(engine, dsh, op, w.omega[op], pairs, deriv=True)
+        _, logv = shg.screen_features(engine, dsh, op, w.omega[op], pairs)
+        torch.cuda.synchronize()
+        off, tot = w.out_offsets()
+        sz = np.asarray(w.block_sizes(), np.int64)
+        mv = _block_absmax(out.cpu().numpy()[:tot], off, sz)
+        md = _block_absmax(dout.cpu().numpy()[:3 * tot], 3 * off, 3 * sz)
+        lb = logb.cpu().numpy().astype(np.float64)
+        m = np.maximum(mv, md)
+        real = m > 1e-300
+        slack = lb[real] - np.log10(m[real])
+        assert slack.min() >= -1e-6, (op, w.name, slack.min())
+        # the derivative-aware bound never lies below the value bound
+        assert np.all(lb >= logv.cpu().numpy() - 1e-6)
+
+
 def test_mlp_forward_and_gradient_match_reference(engine):
     import torch
     from paper_1701_06588_amd import shg
@@ -121,3 +154,89 @@ def test_screened_plan(engine, op):
     assert plan2.n_skipped > 0 or op == "erfc"
     plan.close()
     plan2.close()
+
+
+@pytest.mark.parametrize("op", ["overlap", "gauss", "coulomb"])
+def test_screened_plan_with_derivatives(engine, op):
+    import torch
+    from paper_1701_06588_amd import shg
+    w = inputs.screen5000(n_atoms=700, box=24.0)
+    print(f"case screened plan deriv op={op} n={len(w.pairs)}", flush=True)
+    pairs, oo, out = _dev(w)
+    dout = torch.empty(3 * out.numel(), dtype=torch.float64, device=out.device)
+    ref, dref = torch.empty_like(out), torch.empty_like(dout)
+    dsh = engine.shells(w.shells)
+    engine.pairs(dsh, op, w.omega[op], pairs, oo, ref, dref)
+    tau = 1e-12
+    out.fill_(float("nan"))
+    dout.fill_(float("nan"))
+    plan = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, dout, shg.PLAN_PERSISTENT, tau=tau)
+    plan.execute()
+    torch.cuda.synchronize()
+    g, r = out.cpu().numpy(), ref.cpu().numpy()
+    dg, dr = dout.cpu().numpy(), dref.cpu().numpy()
+    skipped = np.zeros(len(w.pairs), bool)
+    skipped[plan.skipped()] = True
+    assert skipped.sum() == plan.n_skipped
+    off, tot = w.out_offsets()
+    sz = np.asarray(w.block_sizes(), np.int64)
+    elem_skip = np.repeat(skipped, sz)
+    assert np.array_equal(g[:tot][~elem_skip], r[:tot][~elem_skip])
+    # kept derivative blocks are bitwise the plain path's; skipped values and derivatives are zero and tiny
+    dsk = np.repeat(skipped, 3 * sz)
+    assert np.array_equal(dg[:3 * tot][~dsk], dr[:3 * tot][~dsk])
+    assert np.all(g[:tot][elem_skip] == 0) and np.all(dg[:3 * tot][dsk] == 0)
+    assert np.all(np.abs(r[:tot][elem_skip]) <= tau) and np.all(np.abs(dr[:3 * tot][dsk]) <= tau)
+    if op != "coulomb":
+        assert plan.n_skipped > 0
+    plan.close()
+
+
+def _model_path():
+    import os
+    from paper_1701_06588_amd import screen
+    return screen.MODEL if os.path.exists(screen.MODEL) else None
+
+
+@pytest.mark.skipif(_model_path() is None, reason="no trained prescreener model in the package")
+def test_ablation_mlp_gains_over_bound(engine):
+    """No screening vs analytic bound vs bound + trained network on a share of
+    the 5000-atom screening workload (same density), Coulomb and erfc, values:
+    the network skips at least as many pairs as the bound alone and more in
+    total, and at tau_blk = 1e-10 / N_candidates the exact missed mass (L1 over
+    all skipped blocks) stays <= 1e-10."""
+    import torch
+    from paper_1701_06588_amd import shg
+    w = inputs.screen5000(n_atoms=1500, box=60.0 * (1500 / 5000) ** (1 / 3))
+    mlp = shg.Mlp(engine, 0)
+    mlp.load(_model_path())
+    pairs, oo, out = _dev(w)
+    dsh = engine.shells(w.shells)
+    off, tot = w.out_offsets()
+    sz = np.asarray(w.block_sizes(), np.int64)
+    ncand = 2 * len(w.pairs)
+    gain = 0
+    for op in ("coulomb", "erfc"):
+        ref = torch.empty_like(out)
+        engine.pairs(dsh, op, w.omega[op], pairs, oo, ref)
+        torch.cuda.synchronize()
+        absref = np.abs(ref.cpu().numpy()[:tot])
+        block_l1 = np.add.reduceat(absref, off)
+        for tau, strict in ((1e-10 / ncand, True), (1e-10, False)):
+            counts = {}
+            for name, model in (("bound", None), ("bound+mlp", mlp)):
+                print(f"case ablation op={op} tau={tau:.3g} {name} n={len(w.pairs)}", flush=True)
+                plan = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, None, shg.PLAN_PERSISTENT,
+                                tau=tau, mlp=model)
+                ids = plan.skipped()
+                counts[name] = len(ids)
+                missed = float(block_l1[ids].sum())
+                if model is None:
+                    # the bound alone is rigorous per block
+                    assert np.all(absref[np.repeat(np.isin(np.arange(len(sz)), ids), sz)] <= tau)
+                if strict:
+                    assert missed <= 1e-10, (op, name, missed)
+                plan.close()
+            assert counts["bound+mlp"] >= counts["bound"], (op, tau, counts)
+            gain += counts["bound+mlp"] - counts["bound"]
+    assert gain > 0
