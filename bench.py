@@ -44,6 +44,38 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persist_five_ops500_traffic.txt")
+
+
+def kernel_source_hash() -> str:
+    """sha256 of the kernel sources; a stored counter summary is only used for
+    the kernel it was taken on"""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1701_06588_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
+    when there is none or the kernel sources changed since it was taken"""
+    if kernel != "shg::k_persist<true>" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.startswith("    ") and not line.strip().startswith("SQ_"):
+            k, v = line.strip().split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -98,13 +130,15 @@ def main():
                     help="pairs per operator timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="skip loading the tuned tile shapes")
     ap.add_argument("--no-ablation", action="store_true", help="skip the screening ablation")
+    ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
+                    help="run one plain device copy of MIB MiB first (calibrates HBM byte counters)")
     ap.add_argument("--paths", default="plain,batched,screened",
                     help="comma list of paths to run (the value needs 'screened')")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this engine runs on one GPU; multi-GPU sharding of the pair list is "
-                                   "described in DESIGN.md but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this engine runs on one GPU; sharding the pair list over several GPUs is "
+                                   "designed but not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
@@ -112,6 +146,12 @@ def main():
     from paper_1701_06588_amd import inputs, shg, workmodel
 
     paths = set(args.paths.split(","))
+    if args.copy_check > 0:
+        src = torch.ones(args.copy_check << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.five_ops500()
     eng = shg.Engine()
     if not args.no_tune:
@@ -207,6 +247,7 @@ def main():
     roofline = roofline_of(name, kms_sum / nl, nbytes, flops, nl)
     roofline["launches_averaged"] = {"ops": gops, "per_op_ms": {op: round(k, 4) for _, k, _, _, op in per}}
     roofline["step_share"] = round(kms_sum / ms_s, 3)
+    roofline["traffic"] = stored_traffic(name)
 
     for p in splans:
         p.close()

@@ -257,7 +257,8 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
     hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(256), 0, s, hist, AAB_NCLASS, cursor, cursor);
     HIP_TRY(c, hipMemcpyAsync(c->host_rb, cursor, (AAB_NCLASS + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(c->host_rb + AAB_NCLASS + 1, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(256), 0, s, n, c->keys, cursor, c->order);
+    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(256), 0, s, n, c->keys, cursor, c->order, nullptr, nullptr,
+                       nullptr);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(s));
     if ((rc = decode_err(c, c->host_rb[AAB_NCLASS + 1], what))) return rc;

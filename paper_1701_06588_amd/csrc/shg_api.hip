@@ -33,21 +33,31 @@ __global__ void k_prep_shells(int nshell, const int32_t *l, const int32_t *nprim
                               const double *exps, const double *coefs, int64_t nprim_total, int lmax, double *w,
                               int32_t *err)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wave per shell: lane q < K^2 takes the primitive pair (q / K, q % K)
+    // of the self-overlap sum, a butterfly adds them up
+    const int i = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64, lane = threadIdx.x % 64;
     if (i >= nshell) return;
-    int li = l[i], K = nprim[i];
-    int64_t o = prim_off[i];
-    if (li < 0 || li > lmax) { atomicOr(err, ERR_SHELL_L); return; }
-    if (K < 1 || K > KMAX || o < 0 || o + K > nprim_total) { atomicOr(err, ERR_SHELL_K); return; }
+    const int li = l[i], K = nprim[i];
+    const int64_t o = prim_off[i];
+    if (li < 0 || li > lmax) { if (lane == 0) atomicOr(err, ERR_SHELL_L); return; }
+    if (K < 1 || K > KMAX || o < 0 || o + K > nprim_total) { if (lane == 0) atomicOr(err, ERR_SHELL_K); return; }
+    bool bad = false;
     for (int k = 0; k < K; ++k) {
         double e = exps[o + k];
-        if (!(e > 0.0) || !(e < 1e300)) { atomicOr(err, ERR_SHELL_EXP); return; }
+        bad |= !(e > 0.0) || !(e < 1e300);
     }
-    double N = shell_norm(li, K, exps + o, coefs + o);
-    for (int k = 0; k < K; ++k) {
-        double a2 = 2.0 * exps[o + k], p = 1.0;
+    if (bad) { if (lane == 0) atomicOr(err, ERR_SHELL_EXP); return; }
+    double t = 0.0;
+    if (lane < K * K) {
+        const int qa = lane / K, qb = lane - qa * K;
+        t = shell_norm_term(li, exps[o + qa], exps[o + qb], coefs[o + qa], coefs[o + qb]);
+    }
+    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
+    if (lane < K) {
+        const double N = shell_norm_from_sum(li, t);
+        double a2 = 2.0 * exps[o + lane], p = 1.0;
         for (int q = 0; q < li; ++q) p *= a2;
-        w[o + k] = N * coefs[o + k] / p;
+        w[o + lane] = N * coefs[o + lane] / p;
     }
 }
 
@@ -109,10 +119,11 @@ __global__ __launch_bounds__(256) void k_scan_bins(const int32_t *hist, int nb, 
 
 // class-sorted order: each workgroup ranks its items per bin in LDS, reserves
 // one contiguous range per non-empty bin with a single global atomic, then
-// writes the pair ids (order inside a bin is unspecified; results do not
-// depend on it)
+// writes the pair ids and (rec non-null) the pair records (order inside a bin
+// is unspecified; results do not depend on it)
 __global__ __launch_bounds__(BIN_TPB) void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor,
-                                                     int32_t *order)
+                                                     int32_t *order, const int32_t *pairs, const int64_t *out_off,
+                                                     PairRec *rec)
 {
     __shared__ int32_t cnt[NBINS + 1];
     __shared__ int32_t gbase[NBINS + 1];
@@ -136,7 +147,11 @@ __global__ __launch_bounds__(BIN_TPB) void k_scatter(int64_t n, const int32_t *k
 #pragma unroll
     for (int it = 0; it < BIN_ITEMS; ++it) {
         int64_t i = base + (int64_t)it * BIN_TPB + threadIdx.x;
-        if (key[it] >= 0) order[gbase[key[it]] + rank[it]] = (int32_t)i;
+        if (key[it] >= 0) {
+            const int32_t pos = gbase[key[it]] + rank[it];
+            order[pos] = (int32_t)i;
+            if (rec) rec[pos] = PairRec{pairs[2 * i], pairs[2 * i + 1], out_off[i]};
+        }
     }
 }
 
@@ -193,6 +208,7 @@ extern "C" void shg_destroy(shg_ctx *c)
     (void)hipFree(c->w2);
     (void)hipFree(c->keys);
     (void)hipFree(c->order);
+    (void)hipFree(c->rec);
     (void)hipFree(c->bins);
     (void)hipFree(c->stats);
     (void)hipFree(c->Pbuf);
@@ -227,7 +243,7 @@ int prep_shells(shg_ctx *c, const shg_shells *sh, int lmax, double *&w, size_t &
     int rc = grow(c, w, cap, (size_t)sh->nprim_total + 1);
     if (rc) return rc;
     if (sh->nshell > 0)
-        hipLaunchKernelGGL(k_prep_shells, dim3((sh->nshell + 255) / 256), dim3(256), 0, c->stream, sh->nshell,
+        hipLaunchKernelGGL(k_prep_shells, dim3((sh->nshell + 3) / 4), dim3(256), 0, c->stream, sh->nshell,
                            sh->l, sh->nprim, sh->prim_off, sh->exps, sh->coefs, sh->nprim_total, lmax, w, c->err);
     return 0;
 }
@@ -262,6 +278,7 @@ static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omeg
 
     if ((rc = grow(c, c->keys, c->keys_cap, (size_t)n))) return rc;
     if ((rc = grow(c, c->order, c->order_cap, (size_t)n))) return rc;
+    if ((rc = grow(c, c->rec, c->rec_cap, (size_t)n))) return rc;
     hipStream_t s = c->stream;
     int32_t *hist = c->bins, *cursor = c->bins + (NBINS_MAX + 1);
     if (c->prof_on) HIP_TRY(c, hipEventRecord(c->ev[0], s));
@@ -276,7 +293,7 @@ static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omeg
     hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(256), 0, s, hist, NBINS, cursor, cursor);
     HIP_TRY(c, hipMemcpyAsync(c->host_rb, cursor, (NBINS + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(c->host_rb + NBINS + 1, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(BIN_TPB), 0, s, n, c->keys, cursor, c->order);
+    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(BIN_TPB), 0, s, n, c->keys, cursor, c->order, pairs, out_off, c->rec);
     if (c->prof_on) HIP_TRY(c, hipEventRecord(c->ev[1], s));
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -285,7 +302,7 @@ static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omeg
     const tile_fn *ttab[5] = {tile_table_la0(), tile_table_la1(), tile_table_la2(), tile_table_la3(),
                               tile_table_la4()};
     const int D = deriv ? 1 : 0;
-    TileArgs ta{pairs, c->order, sh->center, sh->nprim, sh->prim_off, sh->exps, c->w, c->boys, out_off, out, dout,
+    TileArgs ta{c->rec, c->order, sh->center, sh->nprim, sh->prim_off, sh->exps, c->w, c->boys, out, dout,
                 omega, (int)op};
     int prev = NCLASS + 2;   // event before the next class launch
     int used[NCLASS];
@@ -372,7 +389,7 @@ static int check_shape(shg_ctx *c, int op, int la, int lb, int deriv, int tp, in
         return set_err(c, SHG_EINVAL, "tile shape: class out of range");
     if (tp != 64 && tp != 128 && tp != 256) return set_err(c, SHG_EINVAL, "tile shape: tp must be 64, 128 or 256");
     if (rows_pp < 1 || rows_pp > 2 * la + 1) return set_err(c, SHG_EINVAL, "tile shape: rows_pp outside [1, 2la+1]");
-    long bytes = (long)tp * 72 + (long)tp * (deriv ? 4 : 1) * rows_pp * (2 * lb + 1) * 8;
+    long bytes = tile_smem_bytes_rt(tp, rows_pp, lb, deriv != 0);
     if (bytes > 160 * 1024) return set_err(c, SHG_EINVAL, "tile shape: needs %ld bytes of LDS (> 160 KiB)", bytes);
     return 0;
 }
@@ -414,7 +431,7 @@ extern "C" int shg_autotune(shg_ctx *c, const shg_shells *sh, shg_op op, double 
     const int D = deriv ? 1 : 0;
     const tile_fn *ttab[5] = {tile_table_la0(), tile_table_la1(), tile_table_la2(), tile_table_la3(),
                               tile_table_la4()};
-    TileArgs ta{pairs, c->order, sh->center, sh->nprim, sh->prim_off, sh->exps, c->w, c->boys, out_off, out, dout,
+    TileArgs ta{c->rec, c->order, sh->center, sh->nprim, sh->prim_off, sh->exps, c->w, c->boys, out, dout,
                 omega, (int)op};
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));

@@ -28,6 +28,7 @@ struct shg_ctx {
     double *w2 = nullptr; size_t w2_cap = 0;         // second shell table (aab aux)
     int32_t *keys = nullptr; size_t keys_cap = 0;
     int32_t *order = nullptr; size_t order_cap = 0;
+    shg::PairRec *rec = nullptr; size_t rec_cap = 0;   // class-sorted pair records
     TileShape shape[5][LMAX + 1][LMAX + 1][2];      // tile shape per (op, la, lb, deriv), autotuned
     char arch[64] = {0};
     double tune_ms[5][LMAX + 1][LMAX + 1][2] = {};
@@ -104,7 +105,8 @@ __global__ void k_prep_shells(int nshell, const int32_t *l, const int32_t *nprim
                               const double *exps, const double *coefs, int64_t nprim_total, int lmax, double *w,
                               int32_t *err);
 __global__ void k_scan_bins(const int32_t *hist, int nb, int32_t *starts, int32_t *cursor);
-__global__ void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor, int32_t *order);
+__global__ void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor, int32_t *order, const int32_t *pairs,
+                          const int64_t *out_off, PairRec *rec);
 // screening decisions (shg_screen.hip): keep[i] = 0 if pair i may be skipped
 // (with deriv the bound also covers the d/dR_a elements and the model is not
 // consulted); work: n * 15 floats of scratch

@@ -4,7 +4,9 @@
 //   k_prep_shells    N_l and folded weights per shell                (shell preparation)
 //   k_classify       class key (la, lb, Ka, Kb) per pair, LDS-aggregated histogram
 //   k_scan_bins      exclusive scan of the histogram
-//   k_scatter        class-sorted order of the pairs
+//   k_scatter        class-sorted order of the pairs and, per sorted position, a
+//                    16-byte record (shell ids, output offset) so that the tile
+//                    kernels read their pairs with coalesced loads
 //   k_tile<la,lb,D>  one launch per class; a workgroup owns a tile of TP shell pairs:
 //     phase 1  G = 256/TP lanes per shell pair evaluate the radial terms of the
 //              primitive pairs (Table S1; Boys by Taylor grid + recurrence) and
@@ -30,16 +32,21 @@ constexpr int NCLASS = (LMAX + 1) * (LMAX + 1);
 constexpr int NBINS = NCLASS * 64;      // (la, lb, Ka-1, Kb-1)
 constexpr int TILE_THREADS = 256;
 
+// class-sorted pair record: shells of the pair and offset of its block
+struct __align__(16) PairRec {
+    int32_t a, b;
+    int64_t off;
+};
+
 struct TileArgs {
-    const int32_t *pairs;      // [n][2]
-    const int32_t *order;      // class-sorted pair ids
+    const PairRec *rec;        // [sorted position] (two-center mode)
+    const int32_t *order;      // class-sorted item ids (three-index mode)
     const double *center;      // [nshell][3]
     const int32_t *nprim;
     const int64_t *prim_off;
     const double *exps;
     const double *w;           // folded weights N_l c / (2 alpha)^l
     const double *tab;         // Boys grid
-    const int64_t *out_off;
     double *out, *dout;
     double omega;
     int op;
@@ -98,10 +105,18 @@ __device__ __forceinline__ void reg_fence(RTab<L> &R, double (&O)[NK], double (&
     asm volatile("" : "+v"(X[0]), "+v"(X[1]), "+v"(X[2]));
 }
 
+// LDS of a tile: per pair 9 doubles (O^(k), k < 6, and X), the block offset,
+// and the staged rows with an odd per-pair stride (conflict-free 8-byte
+// accesses when consecutive lanes take consecutive pairs)
+constexpr int SO_STRIDE = 9;
+inline constexpr int tile_smem_bytes_rt(int tp, int rows_pp, int lb, bool D)
+{
+    return tp * SO_STRIDE * 8 + tp * 8 + tp * (((D ? 4 : 1) * rows_pp * (2 * lb + 1)) | 1) * 8;
+}
 template <int LA, int LB, bool D>
 constexpr int tile_smem_bytes(int tp, int rows_pp)
 {
-    return tp * 8 * 8 + tp * 8 + tp * (D ? 4 : 1) * rows_pp * (2 * LB + 1) * 8;
+    return tile_smem_bytes_rt(tp, rows_pp, LB, D);
 }
 
 // One tile of `tcount` (<= shape.tp) class-(LA,LB) pairs starting at sorted
@@ -111,11 +126,12 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
                                            char *smem)
 {
     using PK = PairK<LA, LB, D>;
+    static_assert(PK::NK + 3 <= SO_STRIDE, "O^(k) and X must fit the per-pair LDS slot");
     constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, SZ = NA * NB, NC = D ? 4 : 1;
     const int TP = shape.tp, rows_pp = shape.rows_pp;
-    double *sO = (double *)smem;                 // [TP][8]
-    int64_t *sOff = (int64_t *)(sO + TP * 8);    // [TP]
-    double *sT = (double *)(sOff + TP);          // [TP][NC][rows_pp * NB]
+    double *sO = (double *)smem;                   // [TP][SO_STRIDE]: O^(k), then X
+    int64_t *sOff = (int64_t *)(sO + TP * SO_STRIDE);   // [TP]
+    double *sT = (double *)(sOff + TP);            // [TP][odd stride]
     const int tid = threadIdx.x;
 
     // ---- phase 1: radial terms and contraction, G lanes per shell pair ----
@@ -125,15 +141,20 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
         for (int i = tid; i < tcount; i += TILE_THREADS) {
             const int64_t pos = tstart + i;
 #pragma unroll
-            for (int k = 0; k < PK::NK; ++k) sO[i * 8 + k] = a.P[(pos - a.ybase) * a.pstride + a.poff + k];
+            for (int k = 0; k < PK::NK; ++k)
+                sO[i * SO_STRIDE + k] = a.P[(pos - a.ybase) * a.pstride + a.poff + k];
+            const int p = a.order[pos];
+            const int sa = a.triples[3 * (int64_t)p], sb = a.triples[3 * (int64_t)p + 2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sO[i * SO_STRIDE + 6 + d] = a.center[3 * sa + d] - a.center[3 * sb + d];
             sOff[i] = (pos - a.ybase) * a.ys + a.yoff;
         }
     } else if constexpr (LA <= LMAX) {
         const int G = TILE_THREADS / TP;
         const int i = tid / G, g = tid - (tid / G) * G;
         const bool live = i < tcount;
-        const int p = a.order[tstart + (live ? i : 0)];
-        const int sa = a.pairs[2 * (int64_t)p], sb = a.pairs[2 * (int64_t)p + 1];
+        const PairRec rc = a.rec[tstart + (live ? i : 0)];
+        const int sa = rc.a, sb = rc.b;
         const double X0 = a.center[3 * sa] - a.center[3 * sb];
         const double X1 = a.center[3 * sa + 1] - a.center[3 * sb + 1];
         const double X2 = a.center[3 * sa + 2] - a.center[3 * sb + 2];
@@ -157,8 +178,11 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
             for (int k = 0; k < PK::NK; ++k) O[k] += __shfl_xor(O[k], m, G);
         if (live && g == 0) {
 #pragma unroll
-            for (int k = 0; k < PK::NK; ++k) sO[i * 8 + k] = O[k];
-            sOff[i] = a.out_off[p];
+            for (int k = 0; k < PK::NK; ++k) sO[i * SO_STRIDE + k] = O[k];
+            sO[i * SO_STRIDE + 6] = X0;
+            sO[i * SO_STRIDE + 7] = X1;
+            sO[i * SO_STRIDE + 8] = X2;
+            sOff[i] = rc.off;
         }
     }
     __syncthreads();
@@ -171,20 +195,11 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
     const bool live = i < tcount;
     double X[3], O[PK::NK];
     {
-        const int p = a.order[tstart + (live ? i : 0)];
-        int sa, sb;
-        if (a.triples) {
-            sa = a.triples[3 * (int64_t)p];
-            sb = a.triples[3 * (int64_t)p + 2];
-        } else {
-            sa = a.pairs[2 * (int64_t)p];
-            sb = a.pairs[2 * (int64_t)p + 1];
-        }
-        X[0] = a.center[3 * sa] - a.center[3 * sb];
-        X[1] = a.center[3 * sa + 1] - a.center[3 * sb + 1];
-        X[2] = a.center[3 * sa + 2] - a.center[3 * sb + 2];
+        const int il = live ? i : 0;
 #pragma unroll
-        for (int k = 0; k < PK::NK; ++k) O[k] = live ? sO[i * 8 + k] : 0.0;
+        for (int k = 0; k < PK::NK; ++k) O[k] = live ? sO[il * SO_STRIDE + k] : 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) X[d] = live ? sO[il * SO_STRIDE + 6 + d] : 0.0;
     }
     RTab<cmax(LA, LB)> R;
     solid_R<cmax(LA, LB)>(X[0], X[1], X[2], R);
@@ -192,6 +207,7 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
     for (int r0 = 0; r0 < NA; r0 += rows_pp) {
         const int r1 = min(NA, r0 + rows_pp);
         const int SEG = (r1 - r0) * NB;
+        const int per = NC * SEG, PS = per | 1;
         static_for<0, SZ>([&](auto EE) {
             constexpr int E = decltype(EE)::value;
             constexpr int IA = E / NB, IB = E % NB;
@@ -201,23 +217,33 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
                 pair_elem<LA, LB, IA, IB, D>(R, O, X, res);
                 if (live) {
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) sT[(i * NC + c) * SEG + (E - r0 * NB)] = res[c];
+                    for (int c = 0; c < NC; ++c) sT[i * PS + c * SEG + (E - r0 * NB)] = res[c];
                 }
             }
         });
         __syncthreads();
         // ---- phase 3: coalesced copy of the LDS tile into the blocks ----
-        const int per = NC * SEG;
+        // thread f takes staged value f = ii * per + rem; (ii, rem) advance by a
+        // fixed step instead of being divided out per value
         const int total = tcount * per;
+        const int qs = TILE_THREADS / per, rs = TILE_THREADS - qs * per;
+        int ii = tid / per, rem = tid - ii * per;
         for (int f = tid; f < total; f += TILE_THREADS) {
-            const int ii = f / per, rem = f - ii * per;
-            const int c = rem / SEG, s = rem - c * SEG;
+            int c = 0;
+            if constexpr (NC == 4) c = (rem >= SEG) + (rem >= 2 * SEG) + (rem >= 3 * SEG);
+            const int sidx = rem - c * SEG;
             const int64_t off = sOff[ii];
-            const double v = sT[f];
+            const double v = sT[ii * PS + rem];
             if (c == 0)
-                a.out[off + r0 * NB + s] = v;
+                a.out[off + r0 * NB + sidx] = v;
             else
-                a.dout[3 * off + (c - 1) * SZ + r0 * NB + s] = v;
+                a.dout[3 * off + (c - 1) * SZ + r0 * NB + sidx] = v;
+            ii += qs;
+            rem += rs;
+            if (rem >= per) {
+                rem -= per;
+                ++ii;
+            }
         }
         __syncthreads();
     }
@@ -251,12 +277,9 @@ void launch_tile(hipStream_t s, const TileArgs &a, int64_t start, int64_t count,
 // default tile shape of class (la, lb, D) under an LDS budget (bytes)
 inline TileShape default_shape(int la, int lb, bool D, int tp, int lds_budget)
 {
-    int NA = 2 * la + 1, NB = 2 * lb + 1, NC = D ? 4 : 1;
-    int fixed = tp * 8 * 8 + tp * 8;
-    int per_row = tp * NC * NB * 8;
-    int rows = (lds_budget - fixed) / per_row;
-    if (rows < 1) rows = 1;
-    if (rows > NA) rows = NA;
+    int NA = 2 * la + 1;
+    int rows = NA;
+    while (rows > 1 && tile_smem_bytes_rt(tp, rows, lb, D) > lds_budget) --rows;
     int passes = (NA + rows - 1) / rows;
     rows = (NA + passes - 1) / passes;
     return TileShape{tp, rows};

@@ -340,24 +340,31 @@ SHG_HD SHG_INL void qhat_acc(const RTab<L> &R, double sgn, double &acc)
 // Shell preparation: N_l (eq. N_l) and the folded weights
 // w_alpha = N_l c_alpha / (2 alpha)^l (eq. O_rab2).
 // ---------------------------------------------------------------------------
-SHG_HD SHG_INL double shell_norm(int l, int K, const double *e, const double *c)
+// N_l = K_l [ sum pi^(1/2) (2l+2)! c c' / (2^(2l+3) (l+1)! (a+a')^(l+3/2)) ]^(-1/2):
+// one term of the sum without the constant factor, and N_l from the summed terms
+SHG_HD SHG_INL double shell_norm_term(int l, double ea, double eb, double ca, double cb)
 {
-    // N_l = K_l [ sum pi^(1/2) (2l+2)! c c' / (2^(2l+3) (l+1)! (a+a')^(l+3/2)) ]^(-1/2)
+    double ab = ea + eb;
+    double pw = ab;
+    for (int q = 0; q < l; ++q) pw *= ab;
+    return ca * cb / (pw * sqrt(ab));
+}
+SHG_HD SHG_INL double shell_norm_from_sum(int l, double s)
+{
     double f2l2 = 1, fl1 = 1, p2 = 1;
     for (int i = 2; i <= 2 * l + 2; ++i) f2l2 *= i;
     for (int i = 2; i <= l + 1; ++i) fl1 *= i;
     for (int i = 0; i < 2 * l + 3; ++i) p2 *= 2;
-    double s = 0;
-    for (int i = 0; i < K; ++i)
-        for (int j = 0; j < K; ++j) {
-            double ab = e[i] + e[j];
-            double pw = ab;
-            for (int q = 0; q < l; ++q) pw *= ab;
-            s += c[i] * c[j] / (pw * sqrt(ab));
-        }
     s *= sqrt(PI) * f2l2 / (p2 * fl1);
     double Kl = sqrt((2 * l + 1) / (4 * PI));
     return Kl / sqrt(s);
+}
+SHG_HD SHG_INL double shell_norm(int l, int K, const double *e, const double *c)
+{
+    double s = 0;
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j) s += shell_norm_term(l, e[i], e[j], c[i], c[j]);
+    return shell_norm_from_sum(l, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -29,6 +29,7 @@ struct shg_plan {
     int deriv = 0;
     int mode = 0;                     // 0 per-class launches, 1 persistent
     int32_t *order = nullptr;         // class-sorted pair ids (plan-owned)
+    PairRec *rec = nullptr;           // class-sorted pair records (plan-owned)
     double *w = nullptr;              // folded weights (plan-owned)
     QTile *queue = nullptr;
     int ntiles = 0;
@@ -48,10 +49,10 @@ static int plan_enqueue(shg_plan *p, hipStream_t s)
     shg_ctx *c = p->ctx;
     const shg_shells *sh = &p->sh;
     if (sh->nshell > 0)
-        hipLaunchKernelGGL(k_prep_shells, dim3((sh->nshell + 255) / 256), dim3(256), 0, s, sh->nshell, sh->l, sh->nprim,
+        hipLaunchKernelGGL(k_prep_shells, dim3((sh->nshell + 3) / 4), dim3(256), 0, s, sh->nshell, sh->l, sh->nprim,
                            sh->prim_off, sh->exps, sh->coefs, sh->nprim_total, LMAX, p->w, c->err);
-    TileArgs ta{p->pairs, p->order, sh->center, sh->nprim, sh->prim_off, sh->exps, p->w, c->boys, p->out_off, p->out,
-                p->dout, p->omega, p->op};
+    TileArgs ta{p->rec, p->order, sh->center, sh->nprim, sh->prim_off, sh->exps, p->w, c->boys, p->out, p->dout,
+                p->omega, p->op};
     if (p->mode == 0) {
         for (int cls = 0; cls < NCLASS; ++cls) {
             int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
@@ -116,7 +117,7 @@ static int plan_build_queue(shg_plan *p)
         const TileShape &t = p->shapes.s[cls];
         int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
         if (b1 > b0) {
-            size_t b = (size_t)t.tp * 72 + (size_t)t.tp * (p->deriv ? 4 : 1) * t.rows_pp * (2 * lb + 1) * 8;
+            size_t b = (size_t)tile_smem_bytes_rt(t.tp, t.rows_pp, lb, p->deriv != 0);
             smem = std::max(smem, b);
         }
         (void)la;
@@ -174,11 +175,14 @@ extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, doub
     for (int cls = 0; cls < NCLASS; ++cls) p->shapes.s[cls] = c->shape[op][cls / (LMAX + 1)][cls % (LMAX + 1)][p->deriv];
     auto fail = [&](int code) { shg_plan_destroy(p); return code; };
     hipError_t e = hipMalloc((void **)&p->order, std::max<int64_t>(n, 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->rec, std::max<int64_t>(n, 1) * sizeof(PairRec));
     if (e == hipSuccess) e = hipMalloc((void **)&p->w, std::max<int64_t>(sh->nprim_total, 1) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&p->counter, 64 * sizeof(int));
     if (e != hipSuccess) return fail(set_err(c, SHG_ENOMEM, "shg_plan_create: %s", hipGetErrorString(e)));
     if (n > 0) {
         e = hipMemcpyAsync(p->order, c->order, n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->rec, c->rec, n * sizeof(PairRec), hipMemcpyDeviceToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return fail(set_err(c, SHG_EDEVICE, "shg_plan_create: %s", hipGetErrorString(e)));
     }
@@ -186,6 +190,15 @@ extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, doub
     if (!(flags & SHG_PLAN_NO_GRAPH) && (rc = plan_capture(p))) return fail(rc);
     *plan = p;
     return 0;
+}
+
+// records of the pairs in `order` (after screening removed some)
+__global__ void k_make_recs(int64_t n, const int32_t *order, const int32_t *pairs, const int64_t *out_off, PairRec *rec)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p = order[i];
+    rec[i] = PairRec{pairs[2 * p], pairs[2 * p + 1], out_off[p]};
 }
 
 __global__ void k_zero_blocks(int64_t ns, const int32_t *ids, const int32_t *pairs, const int32_t *l,
@@ -245,8 +258,13 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
         new_start[NCLASS] = (int64_t)korder.size();
         nskip = (int64_t)skipped.size();
         p->skipped = skipped;
-        if (!korder.empty())
-            HIP_TRY(c, hipMemcpy(p->order, korder.data(), korder.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (!korder.empty()) {
+            const int64_t nk = (int64_t)korder.size();
+            HIP_TRY(c, hipMemcpy(p->order, korder.data(), nk * sizeof(int32_t), hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(k_make_recs, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, c->stream, nk, p->order,
+                               pairs, out_off, p->rec);
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
         for (int cls = 0; cls <= NCLASS; ++cls) p->cls_start[cls] = new_start[cls];
         if (nskip > 0) {
             int32_t *ids = nullptr;
@@ -360,8 +378,8 @@ extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
-    TileArgs ta{p->pairs, p->order, p->sh.center, p->sh.nprim, p->sh.prim_off, p->sh.exps, p->w, c->boys,
-                p->out_off, p->out, p->dout, p->omega, p->op};
+    TileArgs ta{p->rec, p->order, p->sh.center, p->sh.nprim, p->sh.prim_off, p->sh.exps, p->w, c->boys, p->out,
+                p->dout, p->omega, p->op};
     double tot = 0;
     for (int r = 0; r < reps; ++r) {
         if (p->mode == 1) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, 1);
@@ -399,6 +417,7 @@ extern "C" void shg_plan_destroy(shg_plan *p)
     plan_free_graph(p);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     (void)hipFree(p->order);
+    (void)hipFree(p->rec);
     (void)hipFree(p->w);
     (void)hipFree(p->queue);
     (void)hipFree(p->counter);
