@@ -130,6 +130,8 @@ def main():
                     help="pairs per operator timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="skip loading the tuned tile shapes")
     ap.add_argument("--no-ablation", action="store_true", help="skip the screening ablation")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the three-index overlap and uneven-molecules measurements")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB first (calibrates HBM byte counters)")
     ap.add_argument("--paths", default="plain,batched,screened",
@@ -305,6 +307,65 @@ def main():
         del ref5, got5
         torch.cuda.synchronize()
 
+    # ---- three-index overlap and uneven molecules (shares of the larger workloads) ----
+    extra = None
+    if not args.no_extra:
+        extra = {}
+        log("three-index overlap")
+        n3 = 250
+        w3 = inputs.aab2000(n_atoms=n3, box=40.0 * (n3 / 2000) ** (1 / 3))
+        off3, tot3 = w3.out_offsets()
+        orb3, aux3 = eng.shells(w3.shells), eng.shells(w3.aux)
+        tri3 = torch.as_tensor(np.ascontiguousarray(w3.triples, np.int32), device=dev)
+        oo3 = torch.as_tensor(off3, device=dev)
+        o3 = torch.empty(tot3, dtype=torch.float64, device=dev)
+        d3 = torch.empty(3 * tot3, dtype=torch.float64, device=dev)
+        nt3 = len(w3.triples)
+        sz = w3.shells.l
+        b3 = int(workmodel.triple_bytes(sz[w3.triples[:, 0]], w3.aux.l[w3.triples[:, 1]],
+                                        sz[w3.triples[:, 2]], True).sum())
+        steps3 = max(2, args.steps // 3)
+        ms3, _ = timed(eng, lambda: eng.aab(orb3, aux3, tri3, oo3, o3, d3), steps3, 1)
+        extra["aab"] = {"workload": f"aab2000 share: {n3} atoms at the 2000-atom density (40 bohr cube), orbital "
+                                    "l 0..3 K 5, RI l 0..6 uncontracted, triples (orbital on X, RI on X, orbital "
+                                    "on Y) of atom pairs within 10 bohr, values + d/dR_A",
+                        "triples": nt3, "ms_per_call": round(ms3, 4),
+                        "triples_per_s": round(nt3 / (ms3 / 1e3), 1),
+                        "alg_bytes_per_call": b3, "hbm_gbs": round(b3 / (ms3 / 1e3) / 1e9, 1),
+                        "hbm_frac": round(b3 / (ms3 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del o3, d3
+        torch.cuda.synchronize()
+        log("uneven molecules")
+        w4 = inputs.molecules256(n_mol=32)
+        off4, tot4 = w4.out_offsets()
+        dsh4 = eng.shells(w4.shells)
+        p4 = torch.as_tensor(np.ascontiguousarray(w4.pairs, np.int32), device=dev)
+        oo4 = torch.as_tensor(off4, device=dev)
+        o4 = torch.empty(tot4, dtype=torch.float64, device=dev)
+        d4 = torch.empty(3 * tot4, dtype=torch.float64, device=dev)
+        n4 = len(w4.pairs)
+        m4 = {"plain": 0.0, "batched": 0.0}
+        modes4 = {}
+        steps4 = max(2, args.steps // 3)
+        for op in ops:
+            ms_p, _ = timed(eng, lambda: eng.pairs(dsh4, op, w4.omega[op], p4, oo4, o4, d4), steps4, 1)
+            pl = shg.Plan(eng, dsh4, op, w4.omega[op], p4, oo4, o4, d4)
+            pl.autotune(2)
+            modes4[op] = pl.mode
+            ms_b, _ = timed(eng, pl.execute, steps4, 1)
+            pl.close()
+            m4["plain"] += ms_p
+            m4["batched"] += ms_b
+        extra["molecules"] = {"workload": "molecules256 share: 32 molecules of 10..400 atoms (log-uniform), "
+                                          "500-atom-workload basis, unordered intra-molecule shell pairs within "
+                                          "12 bohr, 5 operators, values + d/dR_a",
+                              "pairs": n4, "blocks_per_step": n4 * len(ops),
+                              "plain_blocks_per_s": round(n4 * len(ops) / (m4["plain"] / 1e3), 1),
+                              "batched_blocks_per_s": round(n4 * len(ops) / (m4["batched"] / 1e3), 1),
+                              "speedup": round(m4["plain"] / m4["batched"], 3), "modes": modes4}
+        del o4, d4
+        torch.cuda.synchronize()
+
     # ---- CPU oracle on a bounded sample of the same pairs ----
     cpu = None
     if args.cpu_sample > 0:
@@ -344,6 +405,7 @@ def main():
         "speedup_vs_plain": round(ms_plain / ms_s, 3),
         "screening": screening,
         "ablation": ablation,
+        "extra": extra,
         "wall_s_timed": round(wall_s, 3),
     }
     print(json.dumps(res), flush=True)
