@@ -122,7 +122,9 @@ int shg_aab(shg_ctx *ctx, const shg_shells *orb, const shg_shells *aux,
  * coefficients written into the same buffers are picked up, but the shells'
  * l and K and the pair list must not change (they are not re-validated).
  *   flags: SHG_PLAN_PERSISTENT  one persistent class-binned kernel over the
- *                               tile queue instead of one launch per class
+ *                               tile queue (64-pair tiles, each class with its
+ *                               compiled tile schedule) instead of one launch
+ *                               per class (with the tuned tile shapes)
  *          SHG_PLAN_NO_GRAPH    enqueue the kernels on every execute */
 #define SHG_PLAN_PERSISTENT 1u
 #define SHG_PLAN_NO_GRAPH   2u

@@ -105,13 +105,21 @@ __device__ __forceinline__ void reg_fence(RTab<L> &R, double (&O)[NK], double (&
     asm volatile("" : "+v"(X[0]), "+v"(X[1]), "+v"(X[2]));
 }
 
-// LDS of a tile: per pair 9 doubles (O^(k), k < 6, and X), the block offset,
+// compiled tile schedule of the two-center classes (tp = 64): block rows per
+// LDS pass, the fastest shapes of a tuning run on the five-operator workload
+constexpr int sched_rows(int la, int lb, bool D)
+{
+    constexpr int rows_d[5][5] = {{1, 1, 1, 1, 1}, {3, 2, 3, 2, 2}, {5, 5, 3, 2, 2}, {7, 5, 3, 2, 2}, {9, 5, 3, 2, 2}};
+    return D ? rows_d[la][lb] : (la == 4 && lb == 4 ? 5 : 2 * la + 1);
+}
+
+// LDS of a tile: per pair 9 doubles (O^(k), k < 6, and X), two block pointers,
 // and the staged rows with an odd per-pair stride (conflict-free 8-byte
 // accesses when consecutive lanes take consecutive pairs)
 constexpr int SO_STRIDE = 9;
 inline constexpr int tile_smem_bytes_rt(int tp, int rows_pp, int lb, bool D)
 {
-    return tp * SO_STRIDE * 8 + tp * 8 + tp * (((D ? 4 : 1) * rows_pp * (2 * lb + 1)) | 1) * 8;
+    return tp * SO_STRIDE * 8 + tp * 16 + tp * (((D ? 4 : 1) * rows_pp * (2 * lb + 1)) | 1) * 8;
 }
 template <int LA, int LB, bool D>
 constexpr int tile_smem_bytes(int tp, int rows_pp)
@@ -121,17 +129,26 @@ constexpr int tile_smem_bytes(int tp, int rows_pp)
 
 // One tile of `tcount` (<= shape.tp) class-(LA,LB) pairs starting at sorted
 // position `tstart`. smem: dynamic LDS of tile_smem_bytes(tp, rows_pp).
-template <int LA, int LB, bool D>
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+// `after_p1` runs once per thread after phase 1 and before the first barrier.
+// FIXED_ROWS > 0 selects the compiled schedule: tp = 64 and FIXED_ROWS block
+// rows per pass, every pass's element list and the waves' shares of it fixed
+// at compile time (no per-element tests at run time); `shape` is then unused.
+template <int LA, int LB, bool D, int FIXED_ROWS = 0, class Hook = NoHook>
 __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, int tcount, TileShape shape,
-                                           char *smem)
+                                           char *smem, const Hook &after_p1 = Hook())
 {
     using PK = PairK<LA, LB, D>;
     static_assert(PK::NK + 3 <= SO_STRIDE, "O^(k) and X must fit the per-pair LDS slot");
     constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, SZ = NA * NB, NC = D ? 4 : 1;
-    const int TP = shape.tp, rows_pp = shape.rows_pp;
+    const int TP = FIXED_ROWS > 0 ? 64 : shape.tp, rows_pp = FIXED_ROWS > 0 ? FIXED_ROWS : shape.rows_pp;
     double *sO = (double *)smem;                   // [TP][SO_STRIDE]: O^(k), then X
-    int64_t *sOff = (int64_t *)(sO + TP * SO_STRIDE);   // [TP]
-    double *sT = (double *)(sOff + TP);            // [TP][odd stride]
+    double **sPv = (double **)(sO + TP * SO_STRIDE);    // [TP] block of the pair in out
+    double **sPd = sPv + TP;                       // [TP] its d/dR_a blocks in dout
+    double *sT = (double *)(sPd + TP);             // [TP][odd stride]
     const int tid = threadIdx.x;
 
     // ---- phase 1: radial terms and contraction, G lanes per shell pair ----
@@ -147,7 +164,9 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
             const int sa = a.triples[3 * (int64_t)p], sb = a.triples[3 * (int64_t)p + 2];
 #pragma unroll
             for (int d = 0; d < 3; ++d) sO[i * SO_STRIDE + 6 + d] = a.center[3 * sa + d] - a.center[3 * sb + d];
-            sOff[i] = (pos - a.ybase) * a.ys + a.yoff;
+            const int64_t off = (pos - a.ybase) * a.ys + a.yoff;
+            sPv[i] = a.out + off;
+            sPd[i] = a.dout ? a.dout + 3 * off : nullptr;
         }
     } else if constexpr (LA <= LMAX) {
         const int G = TILE_THREADS / TP;
@@ -182,9 +201,11 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
             sO[i * SO_STRIDE + 6] = X0;
             sO[i * SO_STRIDE + 7] = X1;
             sO[i * SO_STRIDE + 8] = X2;
-            sOff[i] = rc.off;
+            sPv[i] = a.out + rc.off;
+            sPd[i] = a.dout ? a.dout + 3 * rc.off : nullptr;
         }
     }
+    after_p1();
     __syncthreads();
 
     // ---- phase 2: angular part; lanes = pairs, waves split the elements ----
@@ -204,48 +225,87 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
     RTab<cmax(LA, LB)> R;
     solid_R<cmax(LA, LB)>(X[0], X[1], X[2], R);
 
-    for (int r0 = 0; r0 < NA; r0 += rows_pp) {
-        const int r1 = min(NA, r0 + rows_pp);
-        const int SEG = (r1 - r0) * NB;
-        const int per = NC * SEG, PS = per | 1;
-        static_for<0, SZ>([&](auto EE) {
-            constexpr int E = decltype(EE)::value;
-            constexpr int IA = E / NB, IB = E % NB;
-            if (IA >= r0 && IA < r1 && ((E - r0 * NB) % EW) == es) {
-                reg_fence<LA, LB, D>(R, O, X);
-                double res[NC];
-                pair_elem<LA, LB, IA, IB, D>(R, O, X, res);
-                if (live) {
+    if constexpr (FIXED_ROWS > 0) {
+        // compiled schedule: tp = 64, so es = wave and i = lane
+        constexpr int NPASS = (NA + FIXED_ROWS - 1) / FIXED_ROWS;
+        static_for<0, NPASS>([&](auto PP) {
+            constexpr int R0 = decltype(PP)::value * FIXED_ROWS;
+            constexpr int R1 = cmin(NA, R0 + FIXED_ROWS);
+            constexpr int SEG = (R1 - R0) * NB, PER = NC * SEG, PS = PER | 1;
+            const auto run = [&](auto WW) {
+                constexpr int W = decltype(WW)::value;
+                static_for<R0 * NB, R1 * NB>([&](auto EE) {
+                    constexpr int E = decltype(EE)::value;
+                    if constexpr ((E - R0 * NB) % 4 == W) {
+                        reg_fence<LA, LB, D>(R, O, X);
+                        double res[NC];
+                        pair_elem<LA, LB, E / NB, E % NB, D>(R, O, X, res);
+                        if (live) {
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) sT[i * PS + c * SEG + (E - r0 * NB)] = res[c];
+                            for (int c = 0; c < NC; ++c) sT[i * PS + c * SEG + (E - R0 * NB)] = res[c];
+                        }
+                    }
+                });
+            };
+            switch (es) {
+            case 0: run(IC<0>{}); break;
+            case 1: run(IC<1>{}); break;
+            case 2: run(IC<2>{}); break;
+            default: run(IC<3>{}); break;
+            }
+            __syncthreads();
+            const int total = tcount * PER;
+            for (int f = tid; f < total; f += TILE_THREADS) {
+                const int ii = f / PER, rem = f - ii * PER;
+                const int c = NC == 4 ? rem / SEG : 0;
+                double *dst = c == 0 ? sPv[ii] : sPd[ii] + (c - 1) * SZ;
+                dst[R0 * NB + rem - c * SEG] = sT[ii * PS + rem];
+            }
+            __syncthreads();
+        });
+    } else {
+        for (int r0 = 0; r0 < NA; r0 += rows_pp) {
+            const int r1 = min(NA, r0 + rows_pp);
+            const int SEG = (r1 - r0) * NB;
+            const int per = NC * SEG, PS = per | 1;
+            static_for<0, SZ>([&](auto EE) {
+                constexpr int E = decltype(EE)::value;
+                constexpr int IA = E / NB, IB = E % NB;
+                if (IA >= r0 && IA < r1 && ((E - r0 * NB) % EW) == es) {
+                    reg_fence<LA, LB, D>(R, O, X);
+                    double res[NC];
+                    pair_elem<LA, LB, IA, IB, D>(R, O, X, res);
+                    if (live) {
+    #pragma unroll
+                        for (int c = 0; c < NC; ++c) sT[i * PS + c * SEG + (E - r0 * NB)] = res[c];
+                    }
+                }
+            });
+            __syncthreads();
+            // ---- phase 3: coalesced copy of the LDS tile into the blocks ----
+            // thread f takes staged value f = ii * per + rem; (ii, rem) advance by a
+            // fixed step instead of being divided out per value, and the destination
+            // is selected without branching
+            const int total = tcount * per;
+            const int qs = TILE_THREADS / per, rs = TILE_THREADS - qs * per;
+            const int rowoff = r0 * NB;
+            int ii = tid / per, rem = tid - ii * per;
+    #pragma unroll 2
+            for (int f = tid; f < total; f += TILE_THREADS) {
+                int c = 0;
+                if constexpr (NC == 4) c = (rem >= SEG) + (rem >= 2 * SEG) + (rem >= 3 * SEG);
+                double *dst = c == 0 ? sPv[ii] : sPd[ii] + (c - 1) * SZ;
+                dst[rowoff + rem - c * SEG] = sT[ii * PS + rem];
+                ii += qs;
+                rem += rs;
+                if (rem >= per) {
+                    rem -= per;
+                    ++ii;
                 }
             }
-        });
-        __syncthreads();
-        // ---- phase 3: coalesced copy of the LDS tile into the blocks ----
-        // thread f takes staged value f = ii * per + rem; (ii, rem) advance by a
-        // fixed step instead of being divided out per value
-        const int total = tcount * per;
-        const int qs = TILE_THREADS / per, rs = TILE_THREADS - qs * per;
-        int ii = tid / per, rem = tid - ii * per;
-        for (int f = tid; f < total; f += TILE_THREADS) {
-            int c = 0;
-            if constexpr (NC == 4) c = (rem >= SEG) + (rem >= 2 * SEG) + (rem >= 3 * SEG);
-            const int sidx = rem - c * SEG;
-            const int64_t off = sOff[ii];
-            const double v = sT[ii * PS + rem];
-            if (c == 0)
-                a.out[off + r0 * NB + sidx] = v;
-            else
-                a.dout[3 * off + (c - 1) * SZ + r0 * NB + sidx] = v;
-            ii += qs;
-            rem += rs;
-            if (rem >= per) {
-                rem -= per;
-                ++ii;
-            }
+            __syncthreads();
         }
-        __syncthreads();
+
     }
 }
 
@@ -255,6 +315,13 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tile(TileArgs a, int64_t start
     extern __shared__ __align__(16) char smem[];
     const int64_t tstart = start + (int64_t)blockIdx.x * shape.tp;
     const int tcount = (int)min((int64_t)shape.tp, start + count - tstart);
+    if constexpr (LA <= LMAX) {
+        constexpr int FR = sched_rows(LA, LB, D);
+        if (shape.tp == 64 && shape.rows_pp == FR && !a.triples) {
+            tile_pairs<LA, LB, D, FR>(a, tstart, tcount, shape, smem);
+            return;
+        }
+    }
     tile_pairs<LA, LB, D>(a, tstart, tcount, shape, smem);
 }
 

@@ -1,12 +1,15 @@
 // shg_persist.h -- persistent, class-binned kernel of the batched path.
 //
-// One launch evaluates every tile of a plan: each workgroup repeatedly takes
+// One launch evaluates every tile of a plan (tiles of 64 pairs, the compiled
+// tile schedule of each class): each workgroup repeatedly takes
 // the next tile index from a device counter (one atomic per tile), reads the
 // tile's class and range from the work queue and runs the class's tile code
-// (tile_pairs, shared with the per-class kernels). All classes of one
-// derivative flavour live in this one kernel; the queue is ordered heaviest
-// class first so that the tail of the launch is made of light tiles. Every
-// workgroup exits once the counter passes the number of tiles.
+// (tile_pairs, shared with the per-class kernels). The index of the following
+// tile is requested when a tile starts and handed over through LDS once phase
+// 1 has waited for its loads, so the atomic's round trip is hidden. All
+// classes of one derivative flavour live in this one kernel; the queue is
+// ordered heaviest class first so that the tail of the launch is made of light
+// tiles. Every workgroup exits once the counter passes the number of tiles.
 #pragma once
 #include "shg_kernels.h"
 
@@ -21,40 +24,42 @@ struct QTile {
 // dynamic LDS limit of the persistent kernel (160 KiB minus its static LDS)
 constexpr int PERSIST_MAX_SMEM = 160 * 1024 - 256;
 
-struct ShapeTable {
-    TileShape s[NCLASS];
-};
-
 template <bool D>
 __global__ __launch_bounds__(TILE_THREADS) void k_persist(TileArgs a, const QTile *__restrict__ q, int ntiles,
-                                                          int *counter, ShapeTable shapes)
+                                                          int *counter)
 {
     extern __shared__ __align__(16) char smem[];
-    __shared__ int s_t;
-    for (;;) {
-        if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
-        __syncthreads();
-        const int t = s_t;
-        __syncthreads();
+    // tile index of iteration k in s_t[k & 1]: written by thread 0 during
+    // iteration k - 1 (after phase 1), read by all after that tile's last barrier
+    __shared__ int s_t[2];
+    if (threadIdx.x == 0) s_t[0] = atomicAdd(counter, 1);
+    __syncthreads();
+    for (int k = 0;; ++k) {
+        const int t = s_t[k & 1];
         if (t >= ntiles) break;
+        int nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(counter, 1);
+        const auto hand_over = [&]() {
+            if (threadIdx.x == 0) s_t[(k + 1) & 1] = nxt;
+        };
         const QTile tile = q[t];
-        const TileShape sh = shapes.s[tile.cls];
         static_for<0, NCLASS>([&](auto CC) {
             constexpr int C = decltype(CC)::value;
-            if (tile.cls == C) tile_pairs<C / (LMAX + 1), C % (LMAX + 1), D>(a, tile.start, tile.count, sh, smem);
+            constexpr int LA = C / (LMAX + 1), LB = C % (LMAX + 1);
+            if (tile.cls == C)
+                tile_pairs<LA, LB, D, sched_rows(LA, LB, D)>(a, tile.start, tile.count, TileShape{64, 1}, smem,
+                                                             hand_over);
         });
     }
 }
 
-typedef void (*persist_fn)(hipStream_t, int grid, size_t smem, const TileArgs &, const QTile *, int, int *,
-                           const ShapeTable &);
+typedef void (*persist_fn)(hipStream_t, int grid, size_t smem, const TileArgs &, const QTile *, int, int *);
 typedef int (*persist_occ_fn)(size_t smem);
 
 template <bool D>
-void launch_persist(hipStream_t s, int grid, size_t smem, const TileArgs &a, const QTile *q, int ntiles, int *counter,
-                    const ShapeTable &shapes)
+void launch_persist(hipStream_t s, int grid, size_t smem, const TileArgs &a, const QTile *q, int ntiles, int *counter)
 {
-    hipLaunchKernelGGL(k_persist<D>, dim3(grid), dim3(TILE_THREADS), smem, s, a, q, ntiles, counter, shapes);
+    hipLaunchKernelGGL(k_persist<D>, dim3(grid), dim3(TILE_THREADS), smem, s, a, q, ntiles, counter);
 }
 
 // also raises the kernel's dynamic-LDS limit (done here, before any graph

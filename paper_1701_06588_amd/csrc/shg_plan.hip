@@ -36,7 +36,7 @@ struct shg_plan {
     int *counter = nullptr;
     int grid = 0;
     size_t smem = 0;
-    ShapeTable shapes{};
+    TileShape shapes[NCLASS] = {};    // per-class launches (tuned shapes)
     int64_t cls_start[NCLASS + 1] = {};
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -57,7 +57,7 @@ static int plan_enqueue(shg_plan *p, hipStream_t s)
         for (int cls = 0; cls < NCLASS; ++cls) {
             int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
             if (b1 <= b0) continue;
-            tile_table(cls / (LMAX + 1))[(cls % (LMAX + 1)) * 2 + p->deriv](s, ta, b0, b1 - b0, p->shapes.s[cls]);
+            tile_table(cls / (LMAX + 1))[(cls % (LMAX + 1)) * 2 + p->deriv](s, ta, b0, b1 - b0, p->shapes[cls]);
         }
     } else if (p->ntiles > 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
@@ -65,7 +65,7 @@ static int plan_enqueue(shg_plan *p, hipStream_t s)
         persist_occ_fn occ;
         if (p->deriv) persist_entry_d1(&f, &occ);
         else persist_entry_d0(&f, &occ);
-        f(s, p->grid, p->smem, ta, p->queue, p->ntiles, p->counter, p->shapes);
+        f(s, p->grid, p->smem, ta, p->queue, p->ntiles, p->counter);
     }
     HIP_TRY(c, hipGetLastError());
     return 0;
@@ -98,7 +98,9 @@ static int plan_capture(shg_plan *p)
     return 0;
 }
 
-// builds the heaviest-class-first tile queue for the current shapes
+// builds the heaviest-class-first tile queue of the persistent kernel: tiles
+// of 64 pairs and the compiled schedule of each class (its LDS need is the
+// dynamic LDS of the launch)
 static int plan_build_queue(shg_plan *p)
 {
     shg_ctx *c = p->ctx;
@@ -111,17 +113,16 @@ static int plan_build_queue(shg_plan *p)
     }
     std::sort(cls_cost.begin(), cls_cost.end());
     size_t smem = 0;
+    constexpr int TP = 64;
     for (auto &cc : cls_cost) {
         int cls = cc.second;
         int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
-        const TileShape &t = p->shapes.s[cls];
         int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
         if (b1 > b0) {
-            size_t b = (size_t)tile_smem_bytes_rt(t.tp, t.rows_pp, lb, p->deriv != 0);
+            size_t b = (size_t)tile_smem_bytes_rt(TP, sched_rows(la, lb, p->deriv != 0), lb, p->deriv != 0);
             smem = std::max(smem, b);
         }
-        (void)la;
-        for (int64_t s0 = b0; s0 < b1; s0 += t.tp) q.push_back(QTile{cls, (int32_t)std::min<int64_t>(t.tp, b1 - s0), s0});
+        for (int64_t s0 = b0; s0 < b1; s0 += TP) q.push_back(QTile{cls, (int32_t)std::min<int64_t>(TP, b1 - s0), s0});
     }
     if (q.size() >= (size_t)1 << 31) return set_err(c, SHG_EINVAL, "plan: too many tiles");
     if (p->queue) { HIP_TRY(c, hipFree(p->queue)); p->queue = nullptr; }
@@ -172,7 +173,7 @@ extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, doub
     p->deriv = deriv ? 1 : 0;
     p->mode = (flags & SHG_PLAN_PERSISTENT) ? 1 : 0;
     for (int cls = 0; cls <= NCLASS; ++cls) p->cls_start[cls] = n > 0 ? c->host_rb[cls * 64] : 0;
-    for (int cls = 0; cls < NCLASS; ++cls) p->shapes.s[cls] = c->shape[op][cls / (LMAX + 1)][cls % (LMAX + 1)][p->deriv];
+    for (int cls = 0; cls < NCLASS; ++cls) p->shapes[cls] = c->shape[op][cls / (LMAX + 1)][cls % (LMAX + 1)][p->deriv];
     auto fail = [&](int code) { shg_plan_destroy(p); return code; };
     hipError_t e = hipMalloc((void **)&p->order, std::max<int64_t>(n, 1) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void **)&p->rec, std::max<int64_t>(n, 1) * sizeof(PairRec));
@@ -389,13 +390,13 @@ extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
             persist_occ_fn occ;
             if (p->deriv) persist_entry_d1(&f, &occ);
             else persist_entry_d0(&f, &occ);
-            if (p->ntiles > 0) f(c->stream, p->grid, p->smem, ta, p->queue, p->ntiles, p->counter, p->shapes);
+            if (p->ntiles > 0) f(c->stream, p->grid, p->smem, ta, p->queue, p->ntiles, p->counter);
         } else {
             for (int cls = 0; cls < NCLASS; ++cls) {
                 int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
                 if (b1 > b0)
                     tile_table(cls / (LMAX + 1))[(cls % (LMAX + 1)) * 2 + p->deriv](c->stream, ta, b0, b1 - b0,
-                                                                                   p->shapes.s[cls]);
+                                                                                   p->shapes[cls]);
             }
         }
         HIP_TRY(c, hipEventRecord(e1, c->stream));
