@@ -48,13 +48,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persist_five_ops500_traffic.txt
 
 
 def kernel_source_hash() -> str:
-    """sha256 of the kernel sources; a stored counter summary is only used for
+    """sha256 of the sources of the persistent kernel (its translation unit and
+    the local headers it includes); a stored counter summary is only used for
     the kernel it was taken on"""
-    import glob
     import hashlib
+    from paper_1701_06588_amd import build
+    tu = os.path.join(ROOT, "paper_1701_06588_amd", "csrc", "shg_persist_d1.hip")
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1701_06588_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
+    for f in sorted(build._deps(tu)):
         h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]

@@ -164,35 +164,77 @@ struct GauntArgs {
     int la, lt, lb, nc, lamin;
 };
 
-// one output double per thread: (triple, component, ma, mt, mb) flattened so that
-// consecutive threads write consecutive elements of the same block
+// one thread per (triple, component, ma, mt) computes the NB outputs of that
+// block row: out[ma][mt][mb] = sum over the Gaunt list of (ma, mt) of
+// G * Y_L[M][mb]. The class's lists (at most 2 terms per L_a value) are staged
+// in LDS; the class is a template parameter so that the index arithmetic
+// divides by constants (32-bit: a chunk holds fewer than 2^31 rows)
+template <int LA, int LT, int LB, int NC>
 __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
 {
-    const int NT = 2 * a.lt + 1, NB = 2 * a.lb + 1, SZ = (2 * a.la + 1) * NT * NB;
-    const int64_t per = (int64_t)a.nc * SZ;
-    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (f >= a.count * per) return;
-    const int64_t q = f / per;
-    const int e = (int)(f - q * per);
-    const int c = e / SZ, rem = e - c * SZ;
-    const int mb = rem % NB, r2 = rem / NB, mt = r2 % NT, ma = r2 / NT;
-    const int2 se = ((const int2 *)a.gidx)[ma * NT + mt];
-    const int64_t ybase = q * a.ys;
-    double v = 0.0;
-    for (int k = se.x; k < se.x + se.y; ++k) {
-        const int L = a.glm[2 * k], M = a.glm[2 * k + 1];
-        const int nL = (L - a.lamin) / 2;
-        const int64_t loff = (int64_t)NB * (nL * (2 * a.lamin + 1) + 2 * nL * (nL - 1));   // sum of (2L'+1) NB, L' < L
-        const int row = (M + L) * NB + mb;
-        const double y = (c == 0) ? a.Yv[ybase + loff + row]
-                                  : a.Yd[3 * (ybase + loff) + (int64_t)(c - 1) * (2 * L + 1) * NB + row];
-        v = fma(a.gg[k], y, v);
+    constexpr int NA = 2 * LA + 1, NT = 2 * LT + 1, NB = 2 * LB + 1, NAT = NA * NT, SZ = NAT * NB;
+    constexpr int ROWS = NC * NAT;
+    constexpr int LAMIN = LA > LT ? LA - LT : LT - LA, NLA = (LA + LT - LAMIN) / 2 + 1, GMAX = NAT * 2 * NLA;
+    __shared__ int2 s_idx[NAT];
+    __shared__ int2 s_lm[GMAX];
+    __shared__ double s_g[GMAX];
+    const int2 *gidx = (const int2 *)a.gidx;
+    const int g0 = gidx[0].x;
+    const int gn = min(GMAX, gidx[NAT - 1].x + gidx[NAT - 1].y - g0);   // lists are contiguous in (ma, mt)
+    for (int t = threadIdx.x; t < NAT; t += 256) {
+        const int2 e = gidx[t];
+        s_idx[t] = make_int2(e.x - g0, e.y);
+    }
+    for (int t = threadIdx.x; t < gn; t += 256) {
+        s_lm[t] = ((const int2 *)a.glm)[g0 + t];
+        s_g[t] = a.gg[g0 + t];
+    }
+    __syncthreads();
+    const int f = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (f >= (int)a.count * ROWS) return;
+    const int q = f / ROWS, r = f - q * ROWS;
+    const int c = r / NAT, amt = r - c * NAT;
+    const int2 se = s_idx[amt];
+    const int64_t ybase = (int64_t)q * a.ys;
+    const double *y = c == 0 ? a.Yv + ybase : a.Yd + 3 * ybase;
+    double v[NB];
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb) v[mb] = 0.0;
+    for (int k = se.x; k < se.x + se.y && k < gn; ++k) {
+        const int L = s_lm[k].x, M = s_lm[k].y;
+        const int nL = (L - LAMIN) / 2;
+        const int loff = NB * (nL * (2 * LAMIN + 1) + 2 * nL * (nL - 1));   // sum of (2L'+1) NB, L' < L
+        const double *row = y + (c == 0 ? loff : 3 * loff + (c - 1) * (2 * L + 1) * NB) + (M + L) * NB;
+        const double g = s_g[k];
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb) v[mb] = fma(g, row[mb], v[mb]);
     }
     const int64_t off = a.out_off[a.order[a.start + q]];
-    if (c == 0)
-        a.out[off + rem] = v;
-    else
-        a.dout[3 * off + (int64_t)(c - 1) * SZ + rem] = v;
+    double *dst = (c == 0 ? a.out + off : a.dout + 3 * off + (int64_t)(c - 1) * SZ) + amt * NB;
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb) dst[mb] = v[mb];
+}
+
+typedef void (*gaunt_fn)(hipStream_t, unsigned grid, const GauntArgs &);
+
+template <int LA, int LT, int LB, int NC>
+void launch_gaunt(hipStream_t s, unsigned grid, const GauntArgs &a)
+{
+    hipLaunchKernelGGL((k_aab_gaunt<LA, LT, LB, NC>), dim3(grid), dim3(256), 0, s, a);
+}
+
+template <int... I>
+const gaunt_fn *make_gaunt_table(std::integer_sequence<int, I...>)
+{
+    // index ((la * 7 + lt) * 4 + lb) * 2 + D
+    static const gaunt_fn t[] = {&launch_gaunt<I / 56, (I / 8) % 7, (I / 2) % 4, (I % 2) ? 4 : 1>...};
+    return t;
+}
+
+const gaunt_fn *gaunt_table()
+{
+    static const gaunt_fn *t = make_gaunt_table(std::make_integer_sequence<int, AAB_NCLASS * 2>{});
+    return t;
 }
 
 int upload_gaunt(shg_ctx *c)
@@ -208,6 +250,8 @@ int upload_gaunt(shg_ctx *c)
             for (int ma = -la; ma <= la; ++ma)
                 for (int mt = -lt; mt <= lt; ++mt) {
                     const auto &ent = G.at(la, lt, ma, mt);
+                    if ((int)ent.size() > 2 * ((la < lt ? la : lt) + 1))
+                        return set_err(c, SHG_EDEVICE, "shg_aab: Gaunt list longer than two terms per L");
                     size_t slot = ((size_t)(la * (AAB_LT + 1) + lt) * maxmm + (ma + la) * (2 * lt + 1) + (mt + lt)) * 2;
                     idx[slot] = (int32_t)gg.size();
                     idx[slot + 1] = (int32_t)ent.size();
@@ -305,8 +349,10 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
                     GauntArgs ga{c->order, out_off, c->gaunt_idx + (size_t)(la * (AAB_LT + 1) + lt) * maxmm * 2,
                                  c->gaunt_lm, c->gaunt_g, c->Yv, deriv ? c->Yd : nullptr, out, dout, c0, cn, ys,
                                  la, lt, lb, NC, lamin};
-                    const int64_t nthreads = cn * NC * (2 * la + 1) * (2 * lt + 1) * NB;
-                    hipLaunchKernelGGL(k_aab_gaunt, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, s, ga);
+                    const int64_t nthreads = cn * NC * (2 * la + 1) * (2 * lt + 1);
+                    if (nthreads >= ((int64_t)1 << 31) - 256)
+                        return set_err(c, SHG_EINVAL, "shg_aab: chunk too large for 32-bit indexing");
+                    gaunt_table()[key * 2 + (deriv ? 1 : 0)](s, (unsigned)((nthreads + 255) / 256), ga);
                 }
             }
     HIP_TRY(c, hipGetLastError());

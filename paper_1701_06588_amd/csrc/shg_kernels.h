@@ -106,11 +106,13 @@ __device__ __forceinline__ void reg_fence(RTab<L> &R, double (&O)[NK], double (&
 }
 
 // compiled tile schedule of the two-center classes (tp = 64): block rows per
-// LDS pass, the fastest shapes of a tuning run on the five-operator workload
+// LDS pass. The persistent kernel holds two workgroups per CU (its register
+// use), so each class stages as many rows as fit in half the LDS (whole blocks
+// without derivatives); measured faster than the per-class tuned shapes
 constexpr int sched_rows(int la, int lb, bool D)
 {
-    constexpr int rows_d[5][5] = {{1, 1, 1, 1, 1}, {3, 2, 3, 2, 2}, {5, 5, 3, 2, 2}, {7, 5, 3, 2, 2}, {9, 5, 3, 2, 2}};
-    return D ? rows_d[la][lb] : (la == 4 && lb == 4 ? 5 : 2 * la + 1);
+    constexpr int rows_d[5][5] = {{1, 1, 1, 1, 1}, {3, 3, 3, 3, 3}, {5, 5, 5, 5, 4}, {7, 7, 7, 5, 4}, {9, 9, 7, 5, 4}};
+    return D ? rows_d[la][lb] : 2 * la + 1;
 }
 
 // LDS of a tile: per pair 9 doubles (O^(k), k < 6, and X), two block pointers,
