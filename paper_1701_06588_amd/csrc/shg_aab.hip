@@ -342,7 +342,7 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
                         ta.ybase = c0;
                         ta.ys = ys;
                         ta.yoff = loff;
-                        TileShape shp = default_shape(L, lb, deriv, 64, 48 * 1024);
+                        TileShape shp{64, sched_rows(L, lb, deriv)};
                         tile_table(L)[lb * 2 + D](s, ta, c0, cn, shp);
                         loff += (int64_t)(2 * L + 1) * NB;
                     }

@@ -105,16 +105,6 @@ __device__ __forceinline__ void reg_fence(RTab<L> &R, double (&O)[NK], double (&
     asm volatile("" : "+v"(X[0]), "+v"(X[1]), "+v"(X[2]));
 }
 
-// compiled tile schedule of the two-center classes (tp = 64): block rows per
-// LDS pass. The persistent kernel holds two workgroups per CU (its register
-// use), so each class stages as many rows as fit in half the LDS (whole blocks
-// without derivatives); measured faster than the per-class tuned shapes
-constexpr int sched_rows(int la, int lb, bool D)
-{
-    constexpr int rows_d[5][5] = {{1, 1, 1, 1, 1}, {3, 3, 3, 3, 3}, {5, 5, 5, 5, 4}, {7, 7, 7, 5, 4}, {9, 9, 7, 5, 4}};
-    return D ? rows_d[la][lb] : 2 * la + 1;
-}
-
 // LDS of a tile: per pair 9 doubles (O^(k), k < 6, and X), two block pointers,
 // and the staged rows with an odd per-pair stride (conflict-free 8-byte
 // accesses when consecutive lanes take consecutive pairs)
@@ -127,6 +117,23 @@ template <int LA, int LB, bool D>
 constexpr int tile_smem_bytes(int tp, int rows_pp)
 {
     return tile_smem_bytes_rt(tp, rows_pp, LB, D);
+}
+
+// compiled tile schedule (tp = 64): block rows per LDS pass. The persistent
+// kernel holds two workgroups per CU (its register use), so each two-center
+// class stages as many rows as fit in half the LDS (whole blocks without
+// derivatives); measured faster than the per-class tuned shapes. The L_a blocks
+// of the three-index overlap (l_a = 5..9, launched per class) take the rows
+// that fit the LDS share of their register-limited occupancy (two workgroups
+// per CU from l_a = 7 with derivatives, three otherwise).
+constexpr int sched_rows(int la, int lb, bool D)
+{
+    constexpr int rows_d[5][5] = {{1, 1, 1, 1, 1}, {3, 3, 3, 3, 3}, {5, 5, 5, 5, 4}, {7, 7, 7, 5, 4}, {9, 9, 7, 5, 4}};
+    if (la <= 4) return D ? rows_d[la][lb] : 2 * la + 1;
+    const int budget = (D && la >= 7) ? 80 * 1024 - 256 : 53 * 1024;
+    int rows = 2 * la + 1;
+    while (rows > 1 && tile_smem_bytes_rt(64, rows, lb, D) > budget) --rows;
+    return rows;
 }
 
 // One tile of `tcount` (<= shape.tp) class-(LA,LB) pairs starting at sorted
@@ -317,14 +324,16 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tile(TileArgs a, int64_t start
     extern __shared__ __align__(16) char smem[];
     const int64_t tstart = start + (int64_t)blockIdx.x * shape.tp;
     const int tcount = (int)min((int64_t)shape.tp, start + count - tstart);
-    if constexpr (LA <= LMAX) {
-        constexpr int FR = sched_rows(LA, LB, D);
-        if (shape.tp == 64 && shape.rows_pp == FR && !a.triples) {
+    constexpr int FR = sched_rows(LA, LB, D);
+    if constexpr (LA > LMAX) {
+        // L_a blocks of the three-index overlap: launched with the compiled schedule only
+        tile_pairs<LA, LB, D, FR>(a, tstart, tcount, shape, smem);
+    } else {
+        if (shape.tp == 64 && shape.rows_pp == FR)
             tile_pairs<LA, LB, D, FR>(a, tstart, tcount, shape, smem);
-            return;
-        }
+        else
+            tile_pairs<LA, LB, D>(a, tstart, tcount, shape, smem);
     }
-    tile_pairs<LA, LB, D>(a, tstart, tcount, shape, smem);
 }
 
 typedef void (*tile_fn)(hipStream_t, const TileArgs &, int64_t start, int64_t count, TileShape shape);
