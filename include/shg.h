@@ -138,12 +138,12 @@ int  shg_plan_execute(shg_plan *plan);        /* asynchronous on the ctx stream 
  * nullable). */
 int  shg_plan_autotune(shg_plan *plan, int reps, double *ms_per_class, double *ms_persistent);
 int  shg_plan_set_mode(shg_plan *plan, int persistent);
-int  shg_plan_mode(const shg_plan *plan);     /* 0 per-class launches, 1 persistent */
+int  shg_plan_mode(const shg_plan *plan);     /* 0 per-class launches, 1 persistent, 2 multi-operator */
 /* ids of the pairs a screened plan skips, written to the host array ids
  * (capacity cap, nullable); returns how many there are */
 int64_t shg_plan_skipped(const shg_plan *plan, int32_t *ids, int64_t cap);
 /* number of pairs a plan evaluates (after screening) and their algorithmic
- * bytes (8 (2la+1)(2lb+1)(1 or 4) + 16 per pair); host pointers */
+ * bytes (8 (2la+1)(2lb+1)(1 or 4) per operator + 16 per pair); host pointers */
 int  shg_plan_stats(const shg_plan *plan, int64_t *kept, int64_t *alg_bytes);
 /* mean duration in ms of the plan's evaluation kernels alone (no shell
  * preparation), timed with HIP events over `reps` runs; synchronous */
@@ -204,6 +204,22 @@ int  shg_plan_create_screened(shg_ctx *ctx, const shg_shells *sh, shg_op op, dou
                               const int32_t *pairs, int64_t n, const int64_t *out_off,
                               double *out, double *dout, unsigned flags, double tau,
                               shg_mlp *mlp, shg_plan **plan, int64_t *n_skipped);
+
+/* Multi-operator plan: nops (1..5) operators ops[o] with ranges omegas[o] on
+ * one pair list, outputs outs[o] (and, douts non-NULL, douts[o]; host arrays
+ * of device pointers, kept by the plan). Creation evaluates every operator once
+ * through shg_pairs / shg_pairs_deriv; execution evaluates all of them with
+ * one persistent kernel that forms each element's angular factors once and
+ * applies every operator's contracted radial terms (blocks are bitwise those
+ * of the single-operator path). tau > 0 screens with the analytic bound: a
+ * pair is skipped (its blocks zeroed once, in every output) only when the
+ * bound of every operator is below tau; tau = 0 keeps every pair. Such a plan
+ * has one mode (shg_plan_set_mode fails; shg_plan_autotune reports its time
+ * as the persistent time and -1 for the per-class time). */
+int  shg_plan_create_multi(shg_ctx *ctx, const shg_shells *sh, int nops, const shg_op *ops,
+                           const double *omegas, const int32_t *pairs, int64_t n,
+                           const int64_t *out_off, double *const *outs, double *const *douts,
+                           double tau, shg_plan **plan, int64_t *n_skipped);
 
 /* ---- tuning and timing ------------------------------------------------- */
 

@@ -186,7 +186,7 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
         const double X0 = a.center[3 * sa] - a.center[3 * sb];
         const double X1 = a.center[3 * sa + 1] - a.center[3 * sb + 1];
         const double X2 = a.center[3 * sa + 2] - a.center[3 * sb + 2];
-        const double R2 = X0 * X0 + X1 * X1 + X2 * X2;
+        const double R2 = fma(X0, X0, fma(X1, X1, X2 * X2));   // fixed rounding order
         const int64_t oa = a.prim_off[sa], ob = a.prim_off[sb];
         const int kb = a.nprim[sb];
         const int P = live ? a.nprim[sa] * kb : 0;

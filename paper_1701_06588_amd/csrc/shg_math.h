@@ -80,6 +80,8 @@ constexpr int BOYS_TAYLOR = 8;
 template <int NLO, int NHI>
 SHG_HD SHG_INL void boys(double T, const double *__restrict__ tab, double (&F)[NHI - NLO + 1])
 {
+    // no implicit multiply-add contraction: every kernel inlining this rounds alike
+#pragma clang fp contract(off)
     static_assert(NHI + BOYS_TAYLOR - 1 < BOYS_NTAB, "Boys table too short");
     double e = exp(-T);
     if (T < BOYS_TMAX) {
@@ -114,6 +116,8 @@ template <int OP, int KLO, int KHI>
 SHG_HD SHG_INL void radial(double a, double b, double R2, double omega, const double *__restrict__ tab,
                            double (&g)[KHI - KLO + 1])
 {
+    // no implicit multiply-add contraction: every kernel inlining this rounds alike
+#pragma clang fp contract(off)
     constexpr int NK = KHI - KLO + 1;
     double p = a + b, ip = 1.0 / p, rho = a * b * ip, T = rho * R2;
     if (OP == OP_OVERLAP || OP == OP_GAUSS) {
@@ -398,6 +402,76 @@ SHG_HD SHG_INL void contract_pair(const double *__restrict__ ea, const double *_
     }
 }
 
+// The operator-independent part of one element: per j the Qhat sum of the
+// value (q) and the three derivative source sums (tx, ty, tz), and the
+// operator-dependent part that combines them with the contracted radial terms.
+// pair_elem = elem_terms + elem_apply, in the same floating-point order.
+template <int LA, int LB, bool D>
+struct ElemTerms {
+    static constexpr int JM = cmin(LA, LB);
+    double q[JM + 1], tx[JM + 1], ty[JM + 1], tz[JM + 1];
+};
+
+template <int LA, int LB, int IA, int IB, bool D, int L>
+SHG_HD SHG_INL void elem_terms(const RTab<L> &R, ElemTerms<LA, LB, D> &T)
+{
+    constexpr int JM = cmin(LA, LB);
+    constexpr int MA = IA - LA, MUA = cabs(MA), TA = MA < 0 ? 1 : 0;
+    constexpr int MB = IB - LB, MUB = cabs(MB), TB = MB < 0 ? 1 : 0;
+    constexpr double SA = TA ? -1.0 : 1.0, SB = TB ? -1.0 : 1.0;
+    static_for<0, JM + 1>([&](auto JJ) {
+        constexpr int J = decltype(JJ)::value;
+        if constexpr (qhat_nz(LA, MUA, TA, LB, MUB, TB, J)) T.q[J] = qhat<LA, MUA, TA, LB, MUB, TB, J>(R);
+        if constexpr (D) {
+            double tx = 0.0, ty = 0.0, tz = 0.0;
+            qhat_acc<LA - 1, MUA + 1, TA, LB, MUB, TB, J>(R, 1.0, tx);
+            qhat_acc<LA - 1, MUA - 1, TA, LB, MUB, TB, J>(R, -1.0, tx);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, TB, J>(R, -1.0, tx);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, TB, J>(R, 1.0, tx);
+            qhat_acc<LA - 1, MUA + 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
+            qhat_acc<LA - 1, MUA - 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, 1 - TB, J>(R, -SB, ty);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, 1 - TB, J>(R, -SB, ty);
+            qhat_acc<LA - 1, MUA, TA, LB, MUB, TB, J>(R, 2.0, tz);
+            qhat_acc<LA, MUA, TA, LB - 1, MUB, TB, J>(R, -2.0, tz);
+            T.tx[J] = tx;
+            T.ty[J] = ty;
+            T.tz[J] = tz;
+        }
+    });
+}
+
+template <int LA, int LB, int IA, int IB, bool D>
+SHG_HD SHG_INL void elem_apply(const ElemTerms<LA, LB, D> &T, const double *O, const double X[3], double *res)
+{
+    using PK = PairK<LA, LB, D>;
+    constexpr int JM = cmin(LA, LB);
+    constexpr int MA = IA - LA, MUA = cabs(MA), TA = MA < 0 ? 1 : 0;
+    constexpr int MB = IB - LB, MUB = cabs(MB), TB = MB < 0 ? 1 : 0;
+    constexpr double AA = A_lm(LA, MUA) * A_lm(LB, MUB);
+    double v = 0.0, v1 = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
+    static_for<0, JM + 1>([&](auto JJ) {
+        constexpr int J = decltype(JJ)::value;
+        constexpr int K0 = LA + LB - J - PK::KLO;
+        if constexpr (qhat_nz(LA, MUA, TA, LB, MUB, TB, J)) {
+            v = fma(O[K0], T.q[J], v);
+            if constexpr (D) v1 = fma(O[K0 + 1], T.q[J], v1);
+        }
+        if constexpr (D) {
+            dx = fma(O[K0], T.tx[J], dx);
+            dy = fma(O[K0], T.ty[J], dy);
+            dz = fma(O[K0], T.tz[J], dz);
+        }
+    });
+    res[0] = AA * v;
+    if constexpr (D) {
+        double t1 = 2.0 * v1;
+        res[1] = AA * fma(t1, X[0], dx);
+        res[2] = AA * fma(t1, X[1], dy);
+        res[3] = AA * fma(t1, X[2], dz);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // One block element (m_a = IA - LA, m_b = IB - LB) of (a|O|b) and, with D, of
 // d/dR_a:
@@ -411,45 +485,9 @@ SHG_HD SHG_INL void contract_pair(const double *__restrict__ ea, const double *_
 template <int LA, int LB, int IA, int IB, bool D, int L>
 SHG_HD SHG_INL void pair_elem(const RTab<L> &R, const double *O, const double X[3], double *res)
 {
-    using PK = PairK<LA, LB, D>;
-    constexpr int JM = cmin(LA, LB);
-    constexpr int MA = IA - LA, MUA = cabs(MA), TA = MA < 0 ? 1 : 0;
-    constexpr int MB = IB - LB, MUB = cabs(MB), TB = MB < 0 ? 1 : 0;
-    constexpr double SA = TA ? -1.0 : 1.0, SB = TB ? -1.0 : 1.0;
-    constexpr double AA = A_lm(LA, MUA) * A_lm(LB, MUB);
-    double v = 0.0, v1 = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
-    static_for<0, JM + 1>([&](auto JJ) {
-        constexpr int J = decltype(JJ)::value;
-        constexpr int K0 = LA + LB - J - PK::KLO;
-        if constexpr (qhat_nz(LA, MUA, TA, LB, MUB, TB, J)) {
-            double q = qhat<LA, MUA, TA, LB, MUB, TB, J>(R);
-            v = fma(O[K0], q, v);
-            if constexpr (D) v1 = fma(O[K0 + 1], q, v1);
-        }
-        if constexpr (D) {
-            double tx = 0.0, ty = 0.0, tz = 0.0;
-            qhat_acc<LA - 1, MUA + 1, TA, LB, MUB, TB, J>(R, 1.0, tx);
-            qhat_acc<LA - 1, MUA - 1, TA, LB, MUB, TB, J>(R, -1.0, tx);
-            qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, TB, J>(R, -1.0, tx);
-            qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, TB, J>(R, 1.0, tx);
-            qhat_acc<LA - 1, MUA + 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
-            qhat_acc<LA - 1, MUA - 1, 1 - TA, LB, MUB, TB, J>(R, SA, ty);
-            qhat_acc<LA, MUA, TA, LB - 1, MUB + 1, 1 - TB, J>(R, -SB, ty);
-            qhat_acc<LA, MUA, TA, LB - 1, MUB - 1, 1 - TB, J>(R, -SB, ty);
-            qhat_acc<LA - 1, MUA, TA, LB, MUB, TB, J>(R, 2.0, tz);
-            qhat_acc<LA, MUA, TA, LB - 1, MUB, TB, J>(R, -2.0, tz);
-            dx = fma(O[K0], tx, dx);
-            dy = fma(O[K0], ty, dy);
-            dz = fma(O[K0], tz, dz);
-        }
-    });
-    res[0] = AA * v;
-    if constexpr (D) {
-        double t1 = 2.0 * v1;
-        res[1] = AA * fma(t1, X[0], dx);
-        res[2] = AA * fma(t1, X[1], dy);
-        res[3] = AA * fma(t1, X[2], dz);
-    }
+    ElemTerms<LA, LB, D> T;
+    elem_terms<LA, LB, IA, IB, D>(R, T);
+    elem_apply<LA, LB, IA, IB, D>(T, O, X, res);
 }
 
 // whole block (host-side use): every element

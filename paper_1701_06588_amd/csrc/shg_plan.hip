@@ -7,12 +7,15 @@
 // shg_plan_autotune:
 //   per-class   the per-class k_tile launches of the plain path, graph-captured
 //   persistent  one k_persist launch over a heaviest-class-first tile queue
+// A multi-operator plan (shg_plan_create_multi) evaluates several operators on
+// the pair list with one k_multi launch over the same queue.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <vector>
 
 #include "shg_ctx.h"
+#include "shg_multi.h"
 #include "shg_persist.h"
 
 using namespace shg;
@@ -27,7 +30,9 @@ struct shg_plan {
     const int64_t *out_off = nullptr;
     double *out = nullptr, *dout = nullptr;
     int deriv = 0;
-    int mode = 0;                     // 0 per-class launches, 1 persistent
+    int mode = 0;                     // 0 per-class launches, 1 persistent, 2 multi-operator
+    int nops = 0;                     // > 0: multi-operator plan
+    MultiOps mops{};
     int32_t *order = nullptr;         // class-sorted pair ids (plan-owned)
     PairRec *rec = nullptr;           // class-sorted pair records (plan-owned)
     double *w = nullptr;              // folded weights (plan-owned)
@@ -53,7 +58,16 @@ static int plan_enqueue(shg_plan *p, hipStream_t s)
                            sh->prim_off, sh->exps, sh->coefs, sh->nprim_total, LMAX, p->w, c->err);
     TileArgs ta{p->rec, p->order, sh->center, sh->nprim, sh->prim_off, sh->exps, p->w, c->boys, p->out, p->dout,
                 p->omega, p->op};
-    if (p->mode == 0) {
+    if (p->nops > 0) {
+        if (p->ntiles > 0) {
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
+            multi_fn f;
+            multi_occ_fn occ;
+            if (p->deriv) multi_entry_d1(&f, &occ);
+            else multi_entry_d0(&f, &occ);
+            f(s, p->grid, ta, p->mops, p->queue, p->ntiles, p->counter);
+        }
+    } else if (p->mode == 0) {
         for (int cls = 0; cls < NCLASS; ++cls) {
             int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
             if (b1 <= b0) continue;
@@ -215,6 +229,53 @@ __global__ void k_zero_blocks(int64_t ns, const int32_t *ids, const int32_t *pai
         for (int e = threadIdx.x % 64; e < 3 * sz; e += 64) dout[3 * off + e] = 0.0;
 }
 
+// keeps the pairs with hkeep[id] != 0: stable compaction of the class-sorted
+// order and records, skipped ids collected, their blocks zeroed in every
+// output of the plan, tile queue rebuilt
+static int plan_compact(shg_plan *p, const std::vector<int32_t> &hkeep, const std::vector<int32_t> &horder,
+                        int64_t *nskip_out)
+{
+    shg_ctx *c = p->ctx;
+    std::vector<int32_t> korder, skipped;
+    korder.reserve(p->n);
+    int64_t new_start[NCLASS + 1];
+    for (int cls = 0; cls < NCLASS; ++cls) {
+        new_start[cls] = (int64_t)korder.size();
+        for (int64_t q = p->cls_start[cls]; q < p->cls_start[cls + 1]; ++q) {
+            int32_t id = horder[q];
+            if (hkeep[id]) korder.push_back(id);
+            else skipped.push_back(id);
+        }
+    }
+    new_start[NCLASS] = (int64_t)korder.size();
+    const int64_t nskip = (int64_t)skipped.size();
+    p->skipped = skipped;
+    if (!korder.empty()) {
+        const int64_t nk = (int64_t)korder.size();
+        HIP_TRY(c, hipMemcpy(p->order, korder.data(), nk * sizeof(int32_t), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_make_recs, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, c->stream, nk, p->order,
+                           p->pairs, p->out_off, p->rec);
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    for (int cls = 0; cls <= NCLASS; ++cls) p->cls_start[cls] = new_start[cls];
+    if (nskip > 0) {
+        int32_t *ids = nullptr;
+        HIP_TRY(c, hipMalloc((void **)&ids, nskip * sizeof(int32_t)));
+        HIP_TRY(c, hipMemcpy(ids, skipped.data(), nskip * sizeof(int32_t), hipMemcpyHostToDevice));
+        const int nout = p->nops > 0 ? p->nops : 1;
+        for (int o = 0; o < nout; ++o) {
+            double *out = p->nops > 0 ? p->mops.out[o] : p->out;
+            double *dout = p->nops > 0 ? p->mops.dout[o] : p->dout;
+            hipLaunchKernelGGL(k_zero_blocks, dim3((unsigned)((nskip + 3) / 4)), dim3(256), 0, c->stream, nskip, ids,
+                               p->pairs, p->sh.l, p->out_off, out, dout);
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        (void)hipFree(ids);
+    }
+    *nskip_out = nskip;
+    return plan_build_queue(p);
+}
+
 extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op op, double omega,
                                         const int32_t *pairs, int64_t n, const int64_t *out_off, double *out,
                                         double *dout, unsigned flags, double tau, shg_mlp *mlp, shg_plan **plan,
@@ -244,41 +305,82 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
         (void)hipFree(work);
         (void)hipFree(keep);
         if (rc) return fail(rc);
-        // stable compaction of the class-sorted order; skipped ids collected
-        std::vector<int32_t> korder, skipped;
-        korder.reserve(n);
-        int64_t new_start[NCLASS + 1];
-        for (int cls = 0; cls < NCLASS; ++cls) {
-            new_start[cls] = (int64_t)korder.size();
-            for (int64_t q = p->cls_start[cls]; q < p->cls_start[cls + 1]; ++q) {
-                int32_t id = horder[q];
-                if (hkeep[id]) korder.push_back(id);
-                else skipped.push_back(id);
-            }
-        }
-        new_start[NCLASS] = (int64_t)korder.size();
-        nskip = (int64_t)skipped.size();
-        p->skipped = skipped;
-        if (!korder.empty()) {
-            const int64_t nk = (int64_t)korder.size();
-            HIP_TRY(c, hipMemcpy(p->order, korder.data(), nk * sizeof(int32_t), hipMemcpyHostToDevice));
-            hipLaunchKernelGGL(k_make_recs, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, c->stream, nk, p->order,
-                               pairs, out_off, p->rec);
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-        }
-        for (int cls = 0; cls <= NCLASS; ++cls) p->cls_start[cls] = new_start[cls];
-        if (nskip > 0) {
-            int32_t *ids = nullptr;
-            HIP_TRY(c, hipMalloc((void **)&ids, nskip * sizeof(int32_t)));
-            HIP_TRY(c, hipMemcpy(ids, skipped.data(), nskip * sizeof(int32_t), hipMemcpyHostToDevice));
-            hipLaunchKernelGGL(k_zero_blocks, dim3((unsigned)((nskip + 3) / 4)), dim3(256), 0, c->stream, nskip, ids,
-                               pairs, sh->l, out_off, out, dout);
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-            (void)hipFree(ids);
-        }
-        if ((rc = plan_build_queue(p))) return fail(rc);
+        if ((rc = plan_compact(p, hkeep, horder, &nskip))) return fail(rc);
     }
     if (!(flags & SHG_PLAN_NO_GRAPH) && (rc = plan_capture(p))) return fail(rc);
+    if (n_skipped) *n_skipped = nskip;
+    *plan = p;
+    return 0;
+}
+
+extern "C" int shg_plan_create_multi(shg_ctx *c, const shg_shells *sh, int nops, const shg_op *ops,
+                                     const double *omegas, const int32_t *pairs, int64_t n, const int64_t *out_off,
+                                     double *const *outs, double *const *douts, double tau, shg_plan **plan,
+                                     int64_t *n_skipped)
+{
+    const char *what = "shg_plan_create_multi";
+    if (!c || !plan) return SHG_EINVAL;
+    *plan = nullptr;
+    if (nops < 1 || nops > MULTI_MAX) return set_err(c, SHG_EINVAL, "%s: 1 to %d operators", what, MULTI_MAX);
+    if (!ops || !omegas || !outs) return set_err(c, SHG_EINVAL, "%s: NULL pointer argument", what);
+    if (tau < 0.0 || !(tau < 1e300)) return set_err(c, SHG_EINVAL, "%s: tau must be >= 0 and finite", what);
+    const bool deriv = douts != nullptr;
+    for (int o = 0; o < nops; ++o)
+        if (!outs[o] || (deriv && !douts[o])) return set_err(c, SHG_EINVAL, "%s: NULL output pointer", what);
+    // every operator once through the plain path: validation and the exact blocks
+    int rc = 0;
+    for (int o = 0; o < nops; ++o) {
+        rc = deriv ? shg_pairs_deriv(c, sh, ops[o], omegas[o], pairs, n, out_off, outs[o], douts[o])
+                   : shg_pairs(c, sh, ops[o], omegas[o], pairs, n, out_off, outs[o]);
+        if (rc) return rc;
+    }
+    shg_plan *p = nullptr;
+    rc = shg_plan_create(c, sh, ops[0], omegas[0], pairs, n, out_off, outs[0], deriv ? douts[0] : nullptr,
+                         SHG_PLAN_NO_GRAPH, &p);
+    if (rc) return rc;
+    auto fail = [&](int code) { shg_plan_destroy(p); return code; };
+    p->nops = nops;
+    p->mode = 2;
+    p->mops.nops = nops;
+    for (int o = 0; o < MULTI_MAX; ++o) {
+        const int oo = o < nops ? o : 0;
+        p->mops.op[o] = (int)ops[oo];
+        p->mops.omega[o] = omegas[oo];
+        p->mops.out[o] = outs[oo];
+        p->mops.dout[o] = deriv ? douts[oo] : nullptr;
+    }
+    int64_t nskip = 0;
+    if (tau > 0.0 && n > 0) {
+        // a pair is skipped only when every operator's bound is below tau
+        int32_t *keep = nullptr;
+        float *work = nullptr;
+        HIP_TRY(c, hipMalloc((void **)&keep, n * sizeof(int32_t)));
+        if (hipMalloc((void **)&work, (size_t)n * 15 * sizeof(float)) != hipSuccess) {
+            (void)hipFree(keep);
+            return fail(set_err(c, SHG_ENOMEM, "%s: out of device memory", what));
+        }
+        std::vector<int32_t> hkeep(n, 0), tmp(n), horder(n);
+        for (int o = 0; o < nops && !rc; ++o) {
+            rc = screen_pairs(c, sh, ops[o], omegas[o], pairs, n, p->deriv, tau, nullptr, keep, work);
+            if (!rc && hipMemcpy(tmp.data(), keep, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+                rc = set_err(c, SHG_EDEVICE, "%s: read-back failed", what);
+            for (int64_t i = 0; i < n && !rc; ++i) hkeep[i] |= tmp[i];
+        }
+        if (!rc && hipMemcpy(horder.data(), p->order, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = set_err(c, SHG_EDEVICE, "%s: read-back failed", what);
+        (void)hipFree(work);
+        (void)hipFree(keep);
+        if (rc) return fail(rc);
+        if ((rc = plan_compact(p, hkeep, horder, &nskip))) return fail(rc);
+    }
+    multi_fn f;
+    multi_occ_fn occ;
+    if (p->deriv) multi_entry_d1(&f, &occ);
+    else multi_entry_d0(&f, &occ);
+    hipDeviceProp_t prop;
+    HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+    p->grid = std::max(1, std::min(p->ntiles, prop.multiProcessorCount * occ()));
+    if ((rc = plan_capture(p))) return fail(rc);
     if (n_skipped) *n_skipped = nskip;
     *plan = p;
     return 0;
@@ -298,6 +400,7 @@ extern "C" int shg_plan_execute(shg_plan *p)
 extern "C" int shg_plan_set_mode(shg_plan *p, int persistent)
 {
     if (!p) return SHG_EINVAL;
+    if (p->nops > 0) return set_err(p->ctx, SHG_EINVAL, "plan: a multi-operator plan has one mode");
     if (persistent && p->smem > (size_t)PERSIST_MAX_SMEM)
         return set_err(p->ctx, SHG_EINVAL, "plan: tile shapes need more LDS than the persistent kernel allows");
     p->mode = persistent ? 1 : 0;
@@ -308,11 +411,20 @@ extern "C" int shg_plan_set_mode(shg_plan *p, int persistent)
     return 0;
 }
 
+extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms);
+
 extern "C" int shg_plan_autotune(shg_plan *p, int reps, double *ms_per_class, double *ms_persistent)
 {
     if (!p) return SHG_EINVAL;
     shg_ctx *c = p->ctx;
     if (reps < 1) reps = 1;
+    if (p->nops > 0) {   // one mode: report its time
+        double ms = 0;
+        int rc = shg_plan_kernel_ms(p, reps, &ms);
+        if (ms_per_class) *ms_per_class = -1.0;
+        if (ms_persistent) *ms_persistent = ms;
+        return rc;
+    }
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
@@ -362,7 +474,7 @@ extern "C" int shg_plan_stats(const shg_plan *p, int64_t *kept, int64_t *alg_byt
         int64_t cnt = p->cls_start[cls + 1] - p->cls_start[cls];
         int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
         k += cnt;
-        b += cnt * ((int64_t)8 * (2 * la + 1) * (2 * lb + 1) * (p->deriv ? 4 : 1) + 16);
+        b += cnt * ((int64_t)8 * (2 * la + 1) * (2 * lb + 1) * (p->deriv ? 4 : 1) * (p->nops > 0 ? p->nops : 1) + 16);
     }
     *kept = k;
     *alg_bytes = b;
@@ -383,9 +495,15 @@ extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
                 p->dout, p->omega, p->op};
     double tot = 0;
     for (int r = 0; r < reps; ++r) {
-        if (p->mode == 1) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, 1);
+        if (p->mode >= 1) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, 1);
         HIP_TRY(c, hipEventRecord(e0, c->stream));
-        if (p->mode == 1) {
+        if (p->nops > 0) {
+            multi_fn f;
+            multi_occ_fn occ;
+            if (p->deriv) multi_entry_d1(&f, &occ);
+            else multi_entry_d0(&f, &occ);
+            if (p->ntiles > 0) f(c->stream, p->grid, ta, p->mops, p->queue, p->ntiles, p->counter);
+        } else if (p->mode == 1) {
             persist_fn f;
             persist_occ_fn occ;
             if (p->deriv) persist_entry_d1(&f, &occ);

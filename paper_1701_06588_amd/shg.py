@@ -20,7 +20,7 @@ EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pair
            "shg_set_tile_shape", "shg_get_tile_shape", "shg_autotune", "shg_tuning_save", "shg_tuning_load",
            "shg_profile_enable", "shg_profile_read", "shg_plan_create", "shg_plan_execute",
            "shg_plan_autotune", "shg_plan_set_mode", "shg_plan_mode", "shg_plan_destroy",
-           "shg_plan_stats", "shg_plan_kernel_ms", "shg_plan_skipped",
+           "shg_plan_stats", "shg_plan_kernel_ms", "shg_plan_skipped", "shg_plan_create_multi",
            "shg_plan_create_screened", "shg_mlp_create", "shg_mlp_destroy", "shg_mlp_params", "shg_mlp_set_norm",
            "shg_mlp_set_margin", "shg_mlp_train_step", "shg_mlp_grad", "shg_mlp_predict", "shg_mlp_save",
            "shg_mlp_load", "shg_screen_features", "shg_block_logmax")
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     lib.shg_plan_destroy.restype = None
     lib.shg_plan_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.shg_plan_kernel_ms.argtypes = [P, I, C.POINTER(C.c_double)]
+    lib.shg_plan_create_multi.argtypes = [P, C.POINTER(ShgShells), I, P, P, P, C.c_int64, P, P, P, C.c_double,
+                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]
     lib.shg_plan_skipped.argtypes = [P, P, C.c_int64]
     lib.shg_plan_skipped.restype = C.c_int64
     lib.shg_plan_create_screened.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, P, P, P,
@@ -266,7 +268,7 @@ class Plan:
 
     @property
     def mode(self) -> str:
-        return "persistent" if self.engine.lib.shg_plan_mode(self.h) == 1 else "per-class"
+        return {0: "per-class", 1: "persistent", 2: "multi"}.get(self.engine.lib.shg_plan_mode(self.h), "?")
 
     def close(self):
         if getattr(self, "h", None):
@@ -278,6 +280,31 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class MultiPlan(Plan):
+    """Several operators on one pair list, one persistent kernel per execution
+    (shg_plan_create_multi); `outs` / `douts` are lists of device tensors, one
+    per operator; tau > 0 screens with the analytic bound (a pair is skipped only
+    when every operator's bound is below tau)."""
+
+    def __init__(self, engine: "Engine", dsh: DeviceShells, ops, omegas, pairs, out_off, outs, douts=None,
+                 tau: float = 0.0):
+        self.engine = engine
+        self.keep = (dsh, pairs, out_off, list(outs), list(douts) if douts is not None else None)
+        nops = len(ops)
+        op_arr = (C.c_int * nops)(*[OPS[o] for o in ops])
+        om_arr = (C.c_double * nops)(*[float(x) for x in omegas])
+        out_arr = (C.c_void_p * nops)(*[o.data_ptr() for o in outs])
+        dout_arr = (C.c_void_p * nops)(*[d.data_ptr() for d in douts]) if douts is not None else None
+        h = C.c_void_p()
+        ns = C.c_int64()
+        engine._check(engine.lib.shg_plan_create_multi(
+            engine.ctx, C.byref(dsh.c), nops, C.cast(op_arr, C.c_void_p), C.cast(om_arr, C.c_void_p), _ptr(pairs),
+            int(pairs.shape[0]), _ptr(out_off), C.cast(out_arr, C.c_void_p),
+            C.cast(dout_arr, C.c_void_p) if dout_arr is not None else None, float(tau), C.byref(h), C.byref(ns)))
+        self.n_skipped = ns.value
+        self.h = h
 
 
 NPARAM = 9217
