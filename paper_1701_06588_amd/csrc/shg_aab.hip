@@ -164,55 +164,69 @@ struct GauntArgs {
     int la, lt, lb, nc, lamin;
 };
 
-// one thread per (triple, component, ma, mt) computes the NB outputs of that
-// block row: out[ma][mt][mb] = sum over the Gaunt list of (ma, mt) of
-// G * Y_L[M][mb]. The class's lists (at most 2 terms per L_a value) are staged
-// in LDS; the class is a template parameter so that the index arithmetic
-// divides by constants (32-bit: a chunk holds fewer than 2^31 rows)
+// A workgroup takes GQ triples and one component (value or one of x, y, z):
+// it stages their Y blocks (every L_a of the class, coalesced reads) and the
+// class's Gaunt lists (at most 2 terms per L_a value) in LDS, then computes
+// out[ma][mt][mb] = sum over the list of (ma, mt) of G * Y_L[M][mb] with
+// consecutive threads on consecutive output elements (coalesced stores). The
+// class is a template parameter so that all index arithmetic is by constants.
+constexpr int GQ = 8;
+
 template <int LA, int LT, int LB, int NC>
 __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
 {
     constexpr int NA = 2 * LA + 1, NT = 2 * LT + 1, NB = 2 * LB + 1, NAT = NA * NT, SZ = NAT * NB;
-    constexpr int ROWS = NC * NAT;
     constexpr int LAMIN = LA > LT ? LA - LT : LT - LA, NLA = (LA + LT - LAMIN) / 2 + 1, GMAX = NAT * 2 * NLA;
+    // offset of the L_a block with index n (L_a = LAMIN + 2n) in a triple's Y: sum of (2L'+1) NB, L' < L_a
+    constexpr auto loffc = [](int n) constexpr { return NB * (n * (2 * LAMIN + 1) + 2 * n * (n - 1)); };
+    constexpr int YS = loffc(NLA);
     __shared__ int2 s_idx[NAT];
     __shared__ int2 s_lm[GMAX];
     __shared__ double s_g[GMAX];
+    __shared__ double sY[GQ * YS];
+    __shared__ int64_t s_off[GQ];
+    const int tid = threadIdx.x;
+    const int c = (int)(blockIdx.x % NC);
+    const int64_t q0 = (int64_t)(blockIdx.x / NC) * GQ;
+    const int nq = (int)min((int64_t)GQ, a.count - q0);
     const int2 *gidx = (const int2 *)a.gidx;
     const int g0 = gidx[0].x;
     const int gn = min(GMAX, gidx[NAT - 1].x + gidx[NAT - 1].y - g0);   // lists are contiguous in (ma, mt)
-    for (int t = threadIdx.x; t < NAT; t += 256) {
+    for (int t = tid; t < NAT; t += 256) {
         const int2 e = gidx[t];
         s_idx[t] = make_int2(e.x - g0, e.y);
     }
-    for (int t = threadIdx.x; t < gn; t += 256) {
+    for (int t = tid; t < gn; t += 256) {
         s_lm[t] = ((const int2 *)a.glm)[g0 + t];
         s_g[t] = a.gg[g0 + t];
     }
-    __syncthreads();
-    const int f = (int)blockIdx.x * 256 + (int)threadIdx.x;
-    if (f >= (int)a.count * ROWS) return;
-    const int q = f / ROWS, r = f - q * ROWS;
-    const int c = r / NAT, amt = r - c * NAT;
-    const int2 se = s_idx[amt];
-    const int64_t ybase = (int64_t)q * a.ys;
-    const double *y = c == 0 ? a.Yv + ybase : a.Yd + 3 * ybase;
-    double v[NB];
+    if (tid < nq) s_off[tid] = a.out_off[a.order[a.start + q0 + tid]];
+    for (int t = tid; t < nq * YS; t += 256) {
+        const int ql = t / YS, r = t - ql * YS;
+        int nL = 0;
 #pragma unroll
-    for (int mb = 0; mb < NB; ++mb) v[mb] = 0.0;
-    for (int k = se.x; k < se.x + se.y && k < gn; ++k) {
-        const int L = s_lm[k].x, M = s_lm[k].y;
-        const int nL = (L - LAMIN) / 2;
-        const int loff = NB * (nL * (2 * LAMIN + 1) + 2 * nL * (nL - 1));   // sum of (2L'+1) NB, L' < L
-        const double *row = y + (c == 0 ? loff : 3 * loff + (c - 1) * (2 * L + 1) * NB) + (M + L) * NB;
-        const double g = s_g[k];
-#pragma unroll
-        for (int mb = 0; mb < NB; ++mb) v[mb] = fma(g, row[mb], v[mb]);
+        for (int n = 1; n < NLA; ++n) nL += r >= loffc(n) ? 1 : 0;
+        const int L = LAMIN + 2 * nL;
+        const int64_t yb = (q0 + ql) * a.ys;
+        sY[t] = c == 0 ? a.Yv[yb + r] : a.Yd[3 * yb + 3 * loffc(nL) + (c - 1) * (2 * L + 1) * NB + (r - loffc(nL))];
     }
-    const int64_t off = a.out_off[a.order[a.start + q]];
-    double *dst = (c == 0 ? a.out + off : a.dout + 3 * off + (int64_t)(c - 1) * SZ) + amt * NB;
-#pragma unroll
-    for (int mb = 0; mb < NB; ++mb) dst[mb] = v[mb];
+    __syncthreads();
+    for (int e = tid; e < nq * SZ; e += 256) {
+        const int ql = e / SZ, rem = e - ql * SZ;
+        const int mb = rem % NB, amt = rem / NB;
+        const int2 se = s_idx[amt];
+        const double *y = sY + ql * YS;
+        double v = 0.0;
+        for (int k = se.x; k < se.x + se.y && k < gn; ++k) {
+            const int L = s_lm[k].x, M = s_lm[k].y;
+            v = fma(s_g[k], y[loffc((L - LAMIN) / 2) + (M + L) * NB + mb], v);
+        }
+        const int64_t off = s_off[ql];
+        if (c == 0)
+            a.out[off + rem] = v;
+        else
+            a.dout[3 * off + (int64_t)(c - 1) * SZ + rem] = v;
+    }
 }
 
 typedef void (*gaunt_fn)(hipStream_t, unsigned grid, const GauntArgs &);
@@ -349,10 +363,11 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
                     GauntArgs ga{c->order, out_off, c->gaunt_idx + (size_t)(la * (AAB_LT + 1) + lt) * maxmm * 2,
                                  c->gaunt_lm, c->gaunt_g, c->Yv, deriv ? c->Yd : nullptr, out, dout, c0, cn, ys,
                                  la, lt, lb, NC, lamin};
-                    const int64_t nthreads = cn * NC * (2 * la + 1) * (2 * lt + 1);
-                    if (nthreads >= ((int64_t)1 << 31) - 256)
-                        return set_err(c, SHG_EINVAL, "shg_aab: chunk too large for 32-bit indexing");
-                    gaunt_table()[key * 2 + (deriv ? 1 : 0)](s, (unsigned)((nthreads + 255) / 256), ga);
+                    const int64_t groups = (cn + GQ - 1) / GQ;
+                    if (ys != (int64_t)NB * (((lamax - lamin) / 2 + 1) * (2 * lamin + 1) +
+                                             2 * ((lamax - lamin) / 2 + 1) * ((lamax - lamin) / 2)))
+                        return set_err(c, SHG_EDEVICE, "shg_aab: inconsistent Y block layout");
+                    gaunt_table()[key * 2 + (deriv ? 1 : 0)](s, (unsigned)(groups * NC), ga);
                 }
             }
     HIP_TRY(c, hipGetLastError());
