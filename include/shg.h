@@ -115,8 +115,8 @@ int shg_aab(shg_ctx *ctx, const shg_shells *orb, const shg_shells *aux,
  * output buffers (all device pointers, kept by reference, owned by the caller
  * and required to outlive the plan). Creation runs shg_pairs / shg_pairs_deriv
  * once (dout NULL: values only), which validates the input and bins the pairs
- * by class, copies the class-sorted order, builds a tile work queue ordered
- * heaviest class first and, unless SHG_PLAN_NO_GRAPH, records the evaluation
+ * by class, copies the class-sorted order, builds a tile work queue (heavy
+ * and light classes alternating) and, unless SHG_PLAN_NO_GRAPH, records the evaluation
  * (shell preparation + class kernels) in a hipGraph. Execution replays it with
  * no host synchronisation and no binning; new centers, exponents or raw
  * coefficients written into the same buffers are picked up, but the shells'

@@ -14,7 +14,7 @@
 //            are bitwise those of shg_pairs_deriv), and stored straight to
 //            every operator's output
 // One barrier after phase 1 and one at the end of a tile; tiles come from the
-// plan's heaviest-class-first queue through an atomic counter, the next index
+// plan's tile queue through an atomic counter, the next index
 // requested at tile start and handed over through LDS after phase 1.
 #pragma once
 #include "shg_kernels.h"

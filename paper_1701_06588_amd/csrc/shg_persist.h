@@ -7,9 +7,9 @@
 // (tile_pairs, shared with the per-class kernels). The index of the following
 // tile is requested when a tile starts and handed over through LDS once phase
 // 1 has waited for its loads, so the atomic's round trip is hidden. All
-// classes of one derivative flavour live in this one kernel; the queue is
-// ordered heaviest class first so that the tail of the launch is made of light
-// tiles. Every workgroup exits once the counter passes the number of tiles.
+// classes of one derivative flavour live in this one kernel; the queue (built
+// by the plan) alternates heavy and light tiles. Every workgroup exits once the
+// counter passes the number of tiles.
 #pragma once
 #include "shg_kernels.h"
 
