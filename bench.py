@@ -217,7 +217,8 @@ def main():
     ms_s, wall_s = timed(eng, lambda: [p.execute() for p in splans], args.steps, args.warmup)
     value = blocks_per_step / (ms_s / 1e3)
     res_paths["batched+screened"] = {"blocks_per_s": round(value, 1), "ms_per_step": round(ms_s, 4),
-                                     "modes": {op: p.mode for op, p in zip(ops, splans)}}
+                                     "modes": {op: p.mode for op, p in zip(ops, splans)},
+                                     "tile_orders": {op: p.tile_order for op, p in zip(ops, splans)}}
 
     # ---- kept blocks bitwise equal to plain; exact missed mass over skipped blocks ----
     screening = {"tau_blk": tau, "rule": "analytic bound over values and d/dR_a < tau_blk", "per_op": {}}

@@ -133,12 +133,16 @@ int  shg_plan_create(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega
                      const int32_t *pairs, int64_t n, const int64_t *out_off,
                      double *out, double *dout, unsigned flags, shg_plan **plan);
 int  shg_plan_execute(shg_plan *plan);        /* asynchronous on the ctx stream */
-/* Times both modes `reps` times with HIP events (synchronous), keeps the
- * faster one (re-recording the graph) and reports both times (host pointers,
- * nullable). */
+/* Times the per-class launches and the persistent kernel with each of the
+ * three tile orders of its queue (heaviest class first; alternating from the
+ * two ends of that order; round robin over the classes), `reps` times each
+ * with HIP events (synchronous), keeps the fastest (re-recording the graph)
+ * and reports the per-class time and the best persistent time (host pointers,
+ * nullable; -1 when the persistent kernel cannot take the plan's tiles). */
 int  shg_plan_autotune(shg_plan *plan, int reps, double *ms_per_class, double *ms_persistent);
 int  shg_plan_set_mode(shg_plan *plan, int persistent);
 int  shg_plan_mode(const shg_plan *plan);     /* 0 per-class launches, 1 persistent, 2 multi-operator */
+int  shg_plan_tile_order(const shg_plan *plan);  /* 0 heaviest first, 1 alternating ends, 2 round robin */
 /* ids of the pairs a screened plan skips, written to the host array ids
  * (capacity cap, nullable); returns how many there are */
 int64_t shg_plan_skipped(const shg_plan *plan, int32_t *ids, int64_t cap);

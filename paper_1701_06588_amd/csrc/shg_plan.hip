@@ -31,6 +31,7 @@ struct shg_plan {
     double *out = nullptr, *dout = nullptr;
     int deriv = 0;
     int mode = 0;                     // 0 per-class launches, 1 persistent, 2 multi-operator
+    int qorder = 1;                   // tile order: 0 heaviest first, 1 alternating ends, 2 round robin
     int nops = 0;                     // > 0: multi-operator plan
     MultiOps mops{};
     int32_t *order = nullptr;         // class-sorted pair ids (plan-owned)
@@ -138,10 +139,10 @@ static int plan_build_queue(shg_plan *p)
         }
         for (int64_t s0 = b0; s0 < b1; s0 += TP) q.push_back(QTile{cls, (int32_t)std::min<int64_t>(TP, b1 - s0), s0});
     }
-    {   // alternate from the two ends of the heaviest-first order: co-resident
+    if (p->qorder == 1) {
+        // alternate from the two ends of the heaviest-first order: co-resident
         // workgroups then mix arithmetic-heavy tiles with light, load/store-bound
-        // ones (measured 5-10% faster than heaviest first), and the launch ends
-        // on tiles of middle weight
+        // ones, and the launch ends on tiles of middle weight
         std::vector<QTile> z;
         z.reserve(q.size());
         size_t lo = 0, hi = q.size();
@@ -149,6 +150,21 @@ static int plan_build_queue(shg_plan *p)
             z.push_back(q[lo++]);
             if (lo < hi) z.push_back(q[--hi]);
         }
+        q.swap(z);
+    } else if (p->qorder == 2) {
+        // round robin over the classes, heaviest class first in every round
+        std::vector<std::vector<QTile>> per(NCLASS);
+        std::vector<int> cls_seq;
+        for (const auto &t : q) {
+            if (per[t.cls].empty()) cls_seq.push_back(t.cls);
+            per[t.cls].push_back(t);
+        }
+        std::vector<QTile> z;
+        z.reserve(q.size());
+        std::vector<size_t> pos(NCLASS, 0);
+        while (z.size() < q.size())
+            for (int cls : cls_seq)
+                if (pos[cls] < per[cls].size()) z.push_back(per[cls][pos[cls]++]);
         q.swap(z);
     }
     if (q.size() >= (size_t)1 << 31) return set_err(c, SHG_EINVAL, "plan: too many tiles");
@@ -441,9 +457,7 @@ extern "C" int shg_plan_autotune(shg_plan *p, int reps, double *ms_per_class, do
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
-    float t[2] = {0, 0};
-    const int nmodes = p->smem > (size_t)PERSIST_MAX_SMEM ? 1 : 2;
-    for (int mode = 0; mode < nmodes; ++mode) {
+    auto time_mode = [&](int mode, float *ms) {
         p->mode = mode;
         int rc = plan_enqueue(p, c->stream);   // warm-up
         if (rc) return rc;
@@ -452,19 +466,44 @@ extern "C" int shg_plan_autotune(shg_plan *p, int reps, double *ms_per_class, do
             if ((rc = plan_enqueue(p, c->stream))) return rc;
         HIP_TRY(c, hipEventRecord(e1, c->stream));
         HIP_TRY(c, hipEventSynchronize(e1));
-        HIP_TRY(c, hipEventElapsedTime(&t[mode], e0, e1));
-        t[mode] /= reps;
+        HIP_TRY(c, hipEventElapsedTime(ms, e0, e1));
+        *ms /= reps;
+        return 0;
+    };
+    float t_class = 0, t_pers = 0;
+    int rc = time_mode(0, &t_class);
+    if (rc) return rc;
+    const bool can_persist = p->smem <= (size_t)PERSIST_MAX_SMEM;
+    if (can_persist) {
+        // the persistent kernel with each tile order of the queue
+        int best_q = p->qorder;
+        float best = 0;
+        for (int qo = 0; qo < 3; ++qo) {
+            p->qorder = qo;
+            if ((rc = plan_build_queue(p))) return rc;
+            float t = 0;
+            if ((rc = time_mode(1, &t))) return rc;
+            if (qo == 0 || t < best) {
+                best = t;
+                best_q = qo;
+            }
+        }
+        p->qorder = best_q;
+        if ((rc = plan_build_queue(p))) return rc;
+        t_pers = best;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (ms_per_class) *ms_per_class = t[0];
-    if (ms_persistent) *ms_persistent = t[1];
-    p->mode = (nmodes == 2 && t[1] < t[0]) ? 1 : 0;
+    if (ms_per_class) *ms_per_class = t_class;
+    if (ms_persistent) *ms_persistent = can_persist ? t_pers : -1.0;
+    p->mode = (can_persist && t_pers < t_class) ? 1 : 0;
     if (p->graph || p->exec) return plan_capture(p);
     return 0;
 }
 
 extern "C" int shg_plan_mode(const shg_plan *p) { return p ? p->mode : SHG_EINVAL; }
+
+extern "C" int shg_plan_tile_order(const shg_plan *p) { return p ? p->qorder : SHG_EINVAL; }
 
 // ids of the pairs a screened plan skips (host array of capacity cap); returns
 // their number (the full count even when cap is smaller)

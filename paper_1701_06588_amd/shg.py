@@ -20,7 +20,7 @@ EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pair
            "shg_set_tile_shape", "shg_get_tile_shape", "shg_autotune", "shg_tuning_save", "shg_tuning_load",
            "shg_profile_enable", "shg_profile_read", "shg_plan_create", "shg_plan_execute",
            "shg_plan_autotune", "shg_plan_set_mode", "shg_plan_mode", "shg_plan_destroy",
-           "shg_plan_stats", "shg_plan_kernel_ms", "shg_plan_skipped", "shg_plan_create_multi",
+           "shg_plan_stats", "shg_plan_kernel_ms", "shg_plan_skipped", "shg_plan_create_multi", "shg_plan_tile_order",
            "shg_plan_create_screened", "shg_mlp_create", "shg_mlp_destroy", "shg_mlp_params", "shg_mlp_set_norm",
            "shg_mlp_set_margin", "shg_mlp_train_step", "shg_mlp_grad", "shg_mlp_predict", "shg_mlp_save",
            "shg_mlp_load", "shg_screen_features", "shg_block_logmax")
@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
     lib.shg_plan_autotune.argtypes = [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.shg_plan_set_mode.argtypes = [P, I]
     lib.shg_plan_mode.argtypes = [P]
+    lib.shg_plan_tile_order.argtypes = [P]
     lib.shg_plan_destroy.argtypes = [P]
     lib.shg_plan_destroy.restype = None
     lib.shg_plan_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -265,6 +266,11 @@ class Plan:
         ms = C.c_double()
         self.engine._check(self.engine.lib.shg_plan_kernel_ms(self.h, reps, C.byref(ms)))
         return ms.value
+
+    @property
+    def tile_order(self) -> str:
+        return {0: "heaviest-first", 1: "alternating", 2: "round-robin"}.get(
+            self.engine.lib.shg_plan_tile_order(self.h), "?")
 
     @property
     def mode(self) -> str:

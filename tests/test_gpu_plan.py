@@ -84,6 +84,16 @@ def test_plan_autotune_selects_a_mode(engine):
     t_cls, t_per = plan.autotune(2)
     assert t_cls > 0 and t_per > 0
     assert plan.mode == ("persistent" if t_per < t_cls else "per-class")
+    assert plan.tile_order in ("heaviest-first", "alternating", "round-robin")
+    plan.set_mode(True)      # the persistent kernel with the chosen tile order
+    plan.execute()
+    torch.cuda.synchronize()
+    ref = torch.empty_like(out)
+    engine.pairs(dsh, "erf", w.omega["erf"], pairs, oo, ref)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    plan.set_mode(t_per < t_cls)
+    out.fill_(float("nan"))
     plan.execute()
     torch.cuda.synchronize()
     ref = torch.empty_like(out)
