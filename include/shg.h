@@ -104,7 +104,10 @@ int shg_pairs_deriv(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
  *   out     block i = (2la+1) x (2la~+1) x (2lb+1) doubles at out[out_off[i]]
  *   dout    nullable; d/dR_A (a and a~ move together) as x, y, z blocks at
  *           dout[3*out_off[i]]
- * Orbital shells: l <= SHG_LMAX_ORB - 1 (= 3); aux shells: l <= SHG_LMAX_AUX. */
+ * Orbital shells: l <= SHG_LMAX_ORB - 1 (= 3); aux shells: l <= SHG_LMAX_AUX.
+ * The work runs on the context's stream and three library-owned side streams
+ * forked from and joined back into it, so to the caller it is ordered on the
+ * context's stream like every other call. */
 int shg_aab(shg_ctx *ctx, const shg_shells *orb, const shg_shells *aux,
             const int32_t *triples, int64_t n, const int64_t *out_off,
             double *out, double *dout);

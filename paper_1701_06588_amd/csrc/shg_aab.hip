@@ -4,7 +4,9 @@
 //   k_prep_shells     weights of the orbital and auxiliary shell tables
 //   k_aab_classify    class key (la, la~, lb) per triple + validation; LDS histogram
 //   k_scan_bins / k_scatter (shared with the two-center path)
-//   per class, in chunks of at most AAB_CHUNK triples:
+//   per class, in chunks of at most AAB_CHUNK triples, the chunks spread over
+//   AAB_NSTREAM streams (own scratch each; fork/join with events on the
+//   context stream, so the call stays ordered on it):
 //     k_aab_radial    G lanes per triple: P^(k)_{La} for every La of the class from
 //                     the primitive triples (eqs. Pa_aba, devsra2ms)
 //     k_tile<La,lb,D> (three-index mode) the two-center blocks Y_La = (La Ma | lb mb)
@@ -322,9 +324,15 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
     if ((rc = decode_err(c, c->host_rb[AAB_NCLASS + 1], what))) return rc;
     std::vector<int32_t> starts(c->host_rb, c->host_rb + AAB_NCLASS + 1);
 
-    if ((rc = grow(c, c->Pbuf, c->Pbuf_cap, (size_t)AAB_CHUNK * AAB_PSTRIDE))) return rc;
-    const aab_rad_fn *rtab = rad_table();
-    const int maxmm = (2 * AAB_LA + 1) * (2 * AAB_LT + 1);
+    // work items (class, chunk); the host work below (sizes, layout checks,
+    // scratch growth) ends before the fork, so no error return leaves a side
+    // stream un-joined
+    struct Item {
+        int key, la, lt, lb, lamin, lamax, w;
+        int64_t c0, cn, ys;
+        double cost;
+    };
+    std::vector<Item> items;
     for (int la = 0; la <= AAB_LA; ++la)
         for (int lt = 0; lt <= AAB_LT; ++lt)
             for (int lb = 0; lb <= AAB_LB; ++lb) {
@@ -334,42 +342,87 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
                 const int lamin = la > lt ? la - lt : lt - la, lamax = la + lt, NB = 2 * lb + 1;
                 int64_t ys = 0;
                 for (int L = lamin; L <= lamax; L += 2) ys += (int64_t)(2 * L + 1) * NB;
-                const int64_t chunk = std::min<int64_t>(AAB_CHUNK, b1 - b0);
-                if ((rc = grow(c, c->Yv, c->Yv_cap, (size_t)(chunk * ys)))) return rc;
-                if (deriv && (rc = grow(c, c->Yd, c->Yd_cap, (size_t)(3 * chunk * ys)))) return rc;
-                for (int64_t c0 = b0; c0 < b1; c0 += chunk) {
-                    const int64_t cn = std::min<int64_t>(chunk, b1 - c0);
-                    AabRadArgs ra{triples, c->order, orb->center, orb->nprim, orb->prim_off, orb->exps, c->w,
-                                  aux->nprim, aux->prim_off, aux->exps, c->w2, c->Pbuf, c0, c0, cn};
-                    rtab[key * 2 + D](s, ra);
-                    int64_t loff = 0;
-                    for (int L = lamin, iL = 0; L <= lamax; L += 2, ++iL) {
-                        TileArgs ta{};
-                        ta.order = c->order;
-                        ta.center = orb->center;
-                        ta.out = c->Yv;
-                        ta.dout = deriv ? c->Yd : nullptr;
-                        ta.triples = triples;
-                        ta.P = c->Pbuf;
-                        ta.pstride = AAB_PSTRIDE;
-                        ta.poff = iL * 8;
-                        ta.ybase = c0;
-                        ta.ys = ys;
-                        ta.yoff = loff;
-                        TileShape shp{64, sched_rows(L, lb, deriv)};
-                        tile_table(L)[lb * 2 + D](s, ta, c0, cn, shp);
-                        loff += (int64_t)(2 * L + 1) * NB;
-                    }
-                    GauntArgs ga{c->order, out_off, c->gaunt_idx + (size_t)(la * (AAB_LT + 1) + lt) * maxmm * 2,
-                                 c->gaunt_lm, c->gaunt_g, c->Yv, deriv ? c->Yd : nullptr, out, dout, c0, cn, ys,
-                                 la, lt, lb, NC, lamin};
-                    const int64_t groups = (cn + GQ - 1) / GQ;
-                    if (ys != (int64_t)NB * (((lamax - lamin) / 2 + 1) * (2 * lamin + 1) +
-                                             2 * ((lamax - lamin) / 2 + 1) * ((lamax - lamin) / 2)))
-                        return set_err(c, SHG_EDEVICE, "shg_aab: inconsistent Y block layout");
-                    gaunt_table()[key * 2 + (deriv ? 1 : 0)](s, (unsigned)(groups * NC), ga);
+                if (ys != (int64_t)NB * (((lamax - lamin) / 2 + 1) * (2 * lamin + 1) +
+                                         2 * ((lamax - lamin) / 2 + 1) * ((lamax - lamin) / 2)))
+                    return set_err(c, SHG_EDEVICE, "shg_aab: inconsistent Y block layout");
+                for (int64_t c0 = b0; c0 < b1; c0 += AAB_CHUNK) {
+                    const int64_t cn = std::min<int64_t>(AAB_CHUNK, b1 - c0);
+                    // Y blocks written and read, output blocks written
+                    const double cost = (double)cn * NC * (double)(ys + (2 * la + 1) * (2 * lt + 1) * NB);
+                    items.push_back({key, la, lt, lb, lamin, lamax, 0, c0, cn, ys, cost});
                 }
             }
+    // largest first onto the least loaded stream
+    std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+    const int nw = (int)std::min<size_t>(AAB_NSTREAM, items.size());
+    double load[AAB_NSTREAM] = {};
+    int64_t need_p[AAB_NSTREAM] = {}, need_y[AAB_NSTREAM] = {};
+    for (Item &it : items) {
+        int w = 0;
+        for (int v = 1; v < nw; ++v)
+            if (load[v] < load[w]) w = v;
+        it.w = w;
+        load[w] += it.cost;
+        need_p[w] = std::max<int64_t>(need_p[w], it.cn * AAB_PSTRIDE);
+        need_y[w] = std::max<int64_t>(need_y[w], it.cn * it.ys);
+    }
+    for (int w = 0; w < nw; ++w) {
+        if ((rc = grow(c, c->Pbuf[w], c->Pbuf_cap[w], (size_t)need_p[w]))) return rc;
+        if ((rc = grow(c, c->Yv[w], c->Yv_cap[w], (size_t)need_y[w]))) return rc;
+        if (deriv && (rc = grow(c, c->Yd[w], c->Yd_cap[w], (size_t)(3 * need_y[w])))) return rc;
+        if (!c->aab_ev[w]) HIP_TRY(c, hipEventCreateWithFlags(&c->aab_ev[w], hipEventDisableTiming));
+        if (w > 0 && !c->aab_side[w - 1])
+            HIP_TRY(c, hipStreamCreateWithFlags(&c->aab_side[w - 1], hipStreamNonBlocking));
+    }
+    hipStream_t ws[AAB_NSTREAM] = {s};
+    for (int w = 1; w < nw; ++w) ws[w] = c->aab_side[w - 1];
+    // fork: the side streams start after the binning on the context stream
+    if (nw > 1) {
+        HIP_TRY(c, hipEventRecord(c->aab_ev[0], s));
+        for (int w = 1; w < nw; ++w) HIP_TRY(c, hipStreamWaitEvent(ws[w], c->aab_ev[0], 0));
+    }
+    const aab_rad_fn *rtab = rad_table();
+    const int maxmm = (2 * AAB_LA + 1) * (2 * AAB_LT + 1);
+    hipError_t first = hipSuccess;
+    for (const Item &it : items) {
+        hipStream_t sw = ws[it.w];
+        const int NB = 2 * it.lb + 1;
+        AabRadArgs ra{triples, c->order, orb->center, orb->nprim, orb->prim_off, orb->exps, c->w,
+                      aux->nprim, aux->prim_off, aux->exps, c->w2, c->Pbuf[it.w], it.c0, it.c0, it.cn};
+        rtab[it.key * 2 + D](sw, ra);
+        int64_t loff = 0;
+        for (int L = it.lamin, iL = 0; L <= it.lamax; L += 2, ++iL) {
+            TileArgs ta{};
+            ta.order = c->order;
+            ta.center = orb->center;
+            ta.out = c->Yv[it.w];
+            ta.dout = deriv ? c->Yd[it.w] : nullptr;
+            ta.triples = triples;
+            ta.P = c->Pbuf[it.w];
+            ta.pstride = AAB_PSTRIDE;
+            ta.poff = iL * 8;
+            ta.ybase = it.c0;
+            ta.ys = it.ys;
+            ta.yoff = loff;
+            TileShape shp{64, sched_rows(L, it.lb, deriv)};
+            tile_table(L)[it.lb * 2 + D](sw, ta, it.c0, it.cn, shp);
+            loff += (int64_t)(2 * L + 1) * NB;
+        }
+        GauntArgs ga{c->order, out_off, c->gaunt_idx + (size_t)(it.la * (AAB_LT + 1) + it.lt) * maxmm * 2,
+                     c->gaunt_lm, c->gaunt_g, c->Yv[it.w], deriv ? c->Yd[it.w] : nullptr, out, dout, it.c0, it.cn,
+                     it.ys, it.la, it.lt, it.lb, NC, it.lamin};
+        const int64_t groups = (it.cn + GQ - 1) / GQ;
+        gaunt_table()[it.key * 2 + D](sw, (unsigned)(groups * NC), ga);
+        const hipError_t e = hipGetLastError();
+        if (first == hipSuccess) first = e;
+    }
+    // join: the context stream continues after every side stream's work
+    for (int w = 1; w < nw; ++w) {
+        const hipError_t e1 = hipEventRecord(c->aab_ev[w], ws[w]);
+        const hipError_t e2 = hipStreamWaitEvent(s, c->aab_ev[w], 0);
+        if (first == hipSuccess) first = e1 != hipSuccess ? e1 : e2;
+    }
+    if (first != hipSuccess) return set_err(c, SHG_EDEVICE, "%s: launch failed: %s", what, hipGetErrorString(first));
     HIP_TRY(c, hipGetLastError());
     return 0;
 }

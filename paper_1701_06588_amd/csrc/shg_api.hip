@@ -211,9 +211,16 @@ extern "C" void shg_destroy(shg_ctx *c)
     (void)hipFree(c->rec);
     (void)hipFree(c->bins);
     (void)hipFree(c->stats);
-    (void)hipFree(c->Pbuf);
-    (void)hipFree(c->Yv);
-    (void)hipFree(c->Yd);
+    for (int w = 0; w < AAB_NSTREAM; ++w) {
+        (void)hipFree(c->Pbuf[w]);
+        (void)hipFree(c->Yv[w]);
+        (void)hipFree(c->Yd[w]);
+        if (c->aab_ev[w]) (void)hipEventDestroy(c->aab_ev[w]);
+        if (w > 0 && c->aab_side[w - 1]) {
+            (void)hipStreamSynchronize(c->aab_side[w - 1]);
+            (void)hipStreamDestroy(c->aab_side[w - 1]);
+        }
+    }
     (void)hipFree(c->gaunt_idx);
     (void)hipFree(c->gaunt_lm);
     (void)hipFree(c->gaunt_g);

@@ -19,6 +19,10 @@ using shg::NCLASS;
 using shg::LMAX;
 using shg::TileShape;
 
+// the three-index overlap spreads its (class, chunk) work items over the
+// context stream and AAB_NSTREAM - 1 side streams, each with its own scratch
+constexpr int AAB_NSTREAM = 4;
+
 struct shg_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -43,9 +47,11 @@ struct shg_ctx {
     int32_t *gaunt_idx = nullptr;    // [(la*7 + lt)][(ma+la)(2lt+1) + mt+lt] -> {start, count}
     int32_t *gaunt_lm = nullptr;     // entries: {L, M}
     double *gaunt_g = nullptr;       // entries: coefficient
-    double *Pbuf = nullptr; size_t Pbuf_cap = 0;   // P^(k)_La per triple
-    double *Yv = nullptr; size_t Yv_cap = 0;       // two-center blocks (La|lb) per triple
-    double *Yd = nullptr; size_t Yd_cap = 0;       // and their d/dR_a
+    double *Pbuf[AAB_NSTREAM] = {}; size_t Pbuf_cap[AAB_NSTREAM] = {};   // P^(k)_La per triple
+    double *Yv[AAB_NSTREAM] = {}; size_t Yv_cap[AAB_NSTREAM] = {};       // two-center blocks (La|lb) per triple
+    double *Yd[AAB_NSTREAM] = {}; size_t Yd_cap[AAB_NSTREAM] = {};       // and their d/dR_a
+    hipStream_t aab_side[AAB_NSTREAM - 1] = {};   // default priority, non-blocking
+    hipEvent_t aab_ev[AAB_NSTREAM] = {};          // [0] fork from the context stream, [w] join of side stream w
     double *stats = nullptr; size_t stats_cap = 0;  // per-shell screening statistics
     int32_t *bins = nullptr;         // [2][NBINS_MAX + 1]: histogram, then cursors
     int32_t *err = nullptr;          // device error flag
