@@ -2,7 +2,7 @@
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package. It computes (a|O|b), its derivatives with
-respect to R_a, and (a b a~) by the plain definitions (Obara-Saika recurrences
+respect to R_a, (a|r_a^{2n}|b) and (a b a~) by the plain definitions (Obara-Saika recurrences
 over Cartesian Gaussians, contraction, Cartesian -> real solid harmonic
 transform, numerical normalisation); see ``shg_oracle.c``. It shares no code
 with the GPU engine.
@@ -34,6 +34,7 @@ def _lib(long_double: bool = False):
                                    C.c_int64, P, P, P]
         lib.shgo_aab.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int32, P, P, P, P, P, P, P,
                                  C.c_int64, P, P, P]
+        lib.shgo_r2n.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int, P, C.c_int64, P, P, P]
         lib.shgo_boys.argtypes = [C.c_int, C.c_double, P]
         lib.shgo_ss_derivs.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_int, P]
@@ -106,6 +107,29 @@ def aab(orb, aux, triples, out_off=None, deriv=False, long_double=False):
                                     _p(dout) if deriv else None)
     if rc != 0:
         raise ValueError(f"oracle shgo_aab failed ({rc})")
+    return (out, dout) if deriv else out
+
+
+def r2n(shells, nr: int, pair_idx, out_off=None, deriv=False, long_double=False):
+    """(a|r_a^{2n}|b) blocks (Sec. II.C) and, with ``deriv``, d/dR_a (the
+    operator moves with a); layout as in ``pairs``."""
+    pair_idx = np.ascontiguousarray(pair_idx, np.int32).reshape(-1, 2)
+    la = shells.l[pair_idx[:, 0]].astype(np.int64)
+    lb = shells.l[pair_idx[:, 1]].astype(np.int64)
+    sz = (2 * la + 1) * (2 * lb + 1)
+    if out_off is None:
+        out_off = np.zeros(len(sz), np.int64)
+        out_off[1:] = np.cumsum(sz[:-1])
+    out_off = np.ascontiguousarray(out_off, np.int64)
+    total = int((out_off + sz).max()) if len(sz) else 0
+    out = np.zeros(total)
+    dout = np.zeros(3 * total) if deriv else None
+    arrs = _shell_arrays(shells)
+    rc = _lib(long_double).shgo_r2n(shells.n, *[_p(a) for a in arrs], int(nr), _p(pair_idx),
+                                    len(pair_idx), _p(out_off), _p(out),
+                                    _p(dout) if deriv else None)
+    if rc != 0:
+        raise ValueError(f"oracle shgo_r2n failed ({rc})")
     return (out, dout) if deriv else out
 
 

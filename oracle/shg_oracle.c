@@ -10,6 +10,7 @@
  *
  *   (a|O|b) = double integral of phi_a(r1) O(r1 - r2) phi_b(r2)
  *                                     (Sec. II.B, eq. contractedr12int)
+ *   (a|r_a^{2n}|b) = integral of phi_a(r) |r - A|^{2n} phi_b(r)   (Sec. II.C)
  *   (a b a~) = integral of phi_a(r) phi_a~(r) phi_b(r)
  *                                     (Sec. II.D, eq. aba_integrals)
  *
@@ -26,6 +27,8 @@
  *         R_ab^2 (Table S1 of the supplement);
  *       - (a b a~): the two Cartesians on A are merged into one Cartesian with
  *         summed powers and exponent alpha + alpha~ (Sec. III), then overlap;
+ *       - (a|r_a^{2n}|b): r_a^{2n} is expanded into Cartesian monomials on A
+ *         (multinomial theorem) merged into the Cartesian of a, then overlap;
  *       - derivatives with respect to A from d/dA_x of the Cartesian primitive:
  *         2 alpha [a+1_x| - a_x [a-1_x|;
  *  2. contraction with the raw coefficients c_alpha;
@@ -755,5 +758,114 @@ int shgo_aab(int32_t norb, const double *oc, const int32_t *ol, const int32_t *o
     }
     free(no);
     free(nx);
+    return 0;
+}
+
+/* (a|r_a^{2n}|b) (Sec. II.C, eq. ara2nb_def): the local operator r_a^{2n} =
+ * (x_A^2 + y_A^2 + z_A^2)^n is centred on A, so it is expanded by the
+ * multinomial theorem into sum_{i+j+k=n} n!/(i!j!k!) x_A^{2i} y_A^{2j} z_A^{2k}
+ * and each term merged into the Cartesian factor of a; then the plain overlap
+ * of the merged Cartesian Gaussians. d/dR_A moves a and the operator together
+ * (both depend on r - A): the derivative of the merged Cartesian as for a
+ * plain Gaussian. a and b come from the same shell table; out, out_off, dout
+ * as in shgo_pairs; n in [0, 8]. */
+int shgo_r2n(int32_t nshell, const double *center, const int32_t *l, const int32_t *nprim,
+             const int64_t *prim_off, const double *exps, const double *coefs, int nr,
+             const int32_t *pairs, int64_t n, const int64_t *out_off, double *out, double *dout)
+{
+    if (n < 0 || nr < 0 || nr > 8) return -1;
+    if (n == 0) return 0;
+    if (check_shells(nshell, l, nprim, 8)) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (pairs[2 * i] < 0 || pairs[2 * i] >= nshell || pairs[2 * i + 1] < 0 || pairs[2 * i + 1] >= nshell)
+            return -1;
+    shells_t sh = {center, l, nprim, prim_off, exps, coefs};
+    real *norm = (real *)malloc(sizeof(real) * (size_t)nshell);
+    /* multinomial terms of (x^2 + y^2 + z^2)^nr */
+    int nterm = 0;
+    int tp[45][3];
+    real tc[45];
+    for (int i = 0; i <= nr; ++i)
+        for (int j = 0; j <= nr - i; ++j) {
+            int k = nr - i - j;
+            tp[nterm][0] = 2 * i; tp[nterm][1] = 2 * j; tp[nterm][2] = 2 * k;
+            tc[nterm++] = fact_r(nr) / (fact_r(i) * fact_r(j) * fact_r(k));
+        }
+#pragma omp parallel
+    {
+        work_t wk;
+        work_init(&wk);
+#pragma omp for schedule(dynamic, 16)
+        for (int s = 0; s < nshell; ++s) norm[s] = shell_norm(&wk, &sh, s);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < n; ++i) {
+            int a = pairs[2 * i], b = pairs[2 * i + 1];
+            int la = l[a], lb = l[b], na = ncart(la), nb = ncart(lb);
+            int ma_n = 2 * la + 1, mb_n = 2 * lb + 1;
+            const double *A = center + 3 * a, *B = center + 3 * b;
+            size_t csz = (size_t)na * nb;
+            real *Cc = (real *)calloc(csz * 4, sizeof(real));
+            int I = la + 2 * nr + 2, J = lb + 1;
+            real *Sx = (real *)malloc(sizeof(real) * I * J);
+            real *Sy = (real *)malloc(sizeof(real) * I * J);
+            real *Sz = (real *)malloc(sizeof(real) * I * J);
+            for (int pa = 0; pa < nprim[a]; ++pa)
+                for (int pb = 0; pb < nprim[b]; ++pb) {
+                    real al = exps[prim_off[a] + pa], be = exps[prim_off[b] + pb];
+                    real cc = (real)coefs[prim_off[a] + pa] * (real)coefs[prim_off[b] + pb];
+                    overlap_1d(al, be, A[0], B[0], I - 1, lb, Sx);
+                    overlap_1d(al, be, A[1], B[1], I - 1, lb, Sy);
+                    overlap_1d(al, be, A[2], B[2], I - 1, lb, Sz);
+                    const real *S1[3] = {Sx, Sy, Sz};
+                    for (int ia = 0; ia < na; ++ia) {
+                        int p[3];
+                        cart_pow(la, ia, &p[0], &p[1], &p[2]);
+                        for (int ib = 0; ib < nb; ++ib) {
+                            int r[3];
+                            cart_pow(lb, ib, &r[0], &r[1], &r[2]);
+                            size_t k = (size_t)ia * nb + ib;
+                            for (int t = 0; t < nterm; ++t) {
+                                real s1[3], d1[3];
+                                for (int d = 0; d < 3; ++d) {
+                                    int m = p[d] + tp[t][d];
+                                    s1[d] = S1[d][m * J + r[d]];
+                                    d1[d] = 2 * al * S1[d][(m + 1) * J + r[d]];
+                                    if (m > 0) d1[d] -= m * S1[d][(m - 1) * J + r[d]];
+                                }
+                                real f = cc * tc[t];
+                                Cc[k] += f * s1[0] * s1[1] * s1[2];
+                                Cc[csz + k] += f * d1[0] * s1[1] * s1[2];
+                                Cc[2 * csz + k] += f * s1[0] * d1[1] * s1[2];
+                                Cc[3 * csz + k] += f * s1[0] * s1[1] * d1[2];
+                            }
+                        }
+                    }
+                }
+            real *Ta = (real *)malloc(sizeof(real) * ma_n * na);
+            real *Tb = (real *)malloc(sizeof(real) * mb_n * nb);
+            solid_harmonic_cart(la, Ta);
+            solid_harmonic_cart(lb, Tb);
+            real f = norm[a] * norm[b];
+            size_t osz = (size_t)ma_n * mb_n;
+            for (int comp = 0; comp < (dout ? 4 : 1); ++comp) {
+                const real *src = Cc + comp * csz;
+                for (int ma = 0; ma < ma_n; ++ma)
+                    for (int mb = 0; mb < mb_n; ++mb) {
+                        real s = 0;
+                        for (int ia = 0; ia < na; ++ia) {
+                            real ta = Ta[ma * na + ia];
+                            if (ta == 0) continue;
+                            for (int ib = 0; ib < nb; ++ib) s += ta * Tb[mb * nb + ib] * src[(size_t)ia * nb + ib];
+                        }
+                        double v = (double)(f * s);
+                        if (comp == 0) out[out_off[i] + ma * mb_n + mb] = v;
+                        else dout[3 * out_off[i] + (comp - 1) * osz + ma * mb_n + mb] = v;
+                    }
+            }
+            free(Cc); free(Sx); free(Sy); free(Sz); free(Ta); free(Tb);
+        }
+        free(wk.V);
+    }
+    free(norm);
     return 0;
 }

@@ -457,3 +457,135 @@ def test_aab_double_vs_long_double():
         s = slice(off[i], off[i] + sz[i])
         sc = max(1.0, np.abs(o2[s]).max())
         assert np.all(np.abs(o1[s] - o2[s]) <= 1e-12 * np.abs(o2[s]) + 1e-14 * sc)
+
+
+# --------------------------------------------------------------------------
+# (a|r_a^{2n}|b) (Sec. II.C, eq. ara2nb_def)
+# --------------------------------------------------------------------------
+def r2n_block(sh, nr, deriv=False, ld=False):
+    la, lb = int(sh.l[0]), int(sh.l[1])
+    r = oracle.r2n(sh, nr, np.array([[0, 1]]), deriv=deriv, long_double=ld)
+    if deriv:
+        return r[0].reshape(2 * la + 1, 2 * lb + 1), r[1].reshape(3, 2 * la + 1, 2 * lb + 1)
+    return r.reshape(2 * la + 1, 2 * lb + 1)
+
+
+@pytest.mark.parametrize("la,lb,nr", [(0, 0, 1), (1, 0, 2), (2, 1, 1), (1, 2, 3), (3, 2, 2),
+                                      (4, 1, 1), (2, 2, 5), (0, 3, 4)])
+def test_r2n_vs_quadrature(la, lb, nr):
+    """Gauss-Hermite quadrature of phi_a |r - A|^{2n} phi_b, with the
+    pointwise (recursion-based) solid harmonics and N_l."""
+    rng = np.random.default_rng(300 + 10 * la + lb + 100 * nr)
+    sh = rand_pair(rng, la, lb, K=2, lo=0.5, hi=2.5, d=1.3)
+    V = r2n_block(sh, nr)
+    A, B = sh.center
+    ea, eb = sh.exps[:2], sh.exps[2:]
+    ca, cb = sh.coefs[:2], sh.coefs[2:]
+    ref = np.zeros_like(V)
+    for alpha, c in zip(ea, ca):
+        pts, W = pw.gh_grid(A, alpha, 60)
+        rA2 = ((pts - A) ** 2).sum(1)
+        fa = pw.shell_values(la, [alpha], [1.0], A, pts) * pw.norm_l(la, ea, ca) / \
+            pw.norm_l(la, [alpha], [1.0]) * c
+        fa = fa * np.exp(alpha * rA2)[None, :] * rA2[None, :] ** nr
+        fb = pw.shell_values(lb, eb, cb, B, pts)
+        ref += (fa * W) @ fb.T
+    assert np.allclose(V, ref, atol=1e-10 * max(1, np.abs(ref).max())), np.abs(V - ref).max()
+
+
+@pytest.mark.parametrize("nr", [1, 2, 3])
+def test_r2n_ss_closed_form(nr):
+    """Normalised primitive s functions: the product of the two Gaussians is a
+    Gaussian of exponent p = a + b centred at P, |P - A| = b R / p, so the
+    integral is S_ss times the 2n-th moment of |x| about A under an isotropic
+    normal law of variance 1/(2p) per axis, i.e. sigma^{2n} times the n-th
+    moment of a non-central chi-square with 3 degrees of freedom and
+    non-centrality lambda = |P - A|^2 / sigma^2."""
+    a, b, R = 0.8, 1.7, 1.1
+    sh = one_pair(0, 0, [a], [1.0], [b], [1.0], [0, 0, 0], [0, 0, R])
+    V = r2n_block(sh, nr)[0, 0]
+    p = a + b
+    Na, Nb = (2 * a / pi) ** 0.75, (2 * b / pi) ** 0.75
+    S = Na * Nb * (pi / p) ** 1.5 * np.exp(-a * b / p * R * R)
+    s2 = 1 / (2 * p)
+    lam = (b * R / p) ** 2 / s2
+    k = 3
+    mom = {1: k + lam,
+           2: (k + lam) ** 2 + 2 * (k + 2 * lam),
+           3: (k + lam) ** 3 + 6 * (k + lam) * (k + 2 * lam) + 8 * (k + 3 * lam)}[nr]
+    ref = S * s2 ** nr * mom
+    assert abs(V - ref) <= 1e-14 * abs(ref), (V, ref)
+
+
+def test_r2n_zero_is_overlap():
+    rng = np.random.default_rng(31)
+    for la, lb in [(0, 0), (2, 1), (4, 3)]:
+        sh = rand_pair(rng, la, lb, K=3)
+        V, DV = r2n_block(sh, 0, deriv=True)
+        S, DS = block(sh, "overlap", deriv=True)
+        assert np.allclose(V, S, rtol=1e-13, atol=1e-15)
+        assert np.allclose(DV, DS, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("la,lb", [(0, 1), (1, 1), (2, 0), (3, 2), (4, 4)])
+def test_r2n_exponent_derivative(la, lb):
+    """For one primitive on a, r_a^2 exp(-alpha r_a^2) = -d/dalpha exp(-alpha r_a^2):
+    (a|r_a^2|b) = -d/dalpha' [ (a|b)(alpha') N(alpha) / N(alpha') ] at alpha' =
+    alpha, with the primitive normalisation N(alpha) proportional to
+    alpha^{(2 la + 3)/4}; 4th-order central difference of the long-double
+    overlap. Likewise r_a^4 from the second derivative."""
+    rng = np.random.default_rng(41 + la + 7 * lb)
+    sh = rand_pair(rng, la, lb, K=3)
+    alpha = 1.3
+    sh.exps[0] = alpha
+    sh.nprim[0] = 1
+    sh.prim_off[1] = 1
+    sh.exps = np.concatenate([[alpha], sh.exps[3:]])
+    sh.coefs = np.concatenate([[1.0], sh.coefs[3:]])
+    V1, V2 = r2n_block(sh, 1), r2n_block(sh, 2)
+
+    def f(ap):
+        s = copy.deepcopy(sh)
+        s.exps[0] = ap
+        return block(s, "overlap", ld=True) * (alpha / ap) ** ((2 * la + 3) / 4)
+
+    h = 2e-3
+    fm2, fm1, f0, fp1, fp2 = (f(alpha + k * h) for k in (-2, -1, 0, 1, 2))
+    d1 = (fm2 - 8 * fm1 + 8 * fp1 - fp2) / (12 * h)
+    d2 = (-fm2 + 16 * fm1 - 30 * f0 + 16 * fp1 - fp2) / (12 * h * h)
+    sc1, sc2 = max(1e-3, np.abs(V1).max()), max(1e-3, np.abs(V2).max())
+    assert np.allclose(V1, -d1, atol=1e-9 * sc1, rtol=1e-8), np.abs(V1 + d1).max()
+    assert np.allclose(V2, d2, atol=2e-6 * sc2, rtol=1e-5), np.abs(V2 - d2).max()
+
+
+def test_r2n_derivative_vs_finite_differences():
+    """d/dR_a (a and the operator's centre move together) against a 4th-order
+    central difference of the long-double values; translation of both centres
+    leaves the values unchanged."""
+    rng = np.random.default_rng(17)
+    for la, lb, nr in [(0, 1, 1), (2, 2, 2), (3, 1, 4), (1, 4, 5), (4, 0, 3)]:
+        sh = rand_pair(rng, la, lb, K=2, lo=0.2, hi=5, d=1.8)
+        V, D = r2n_block(sh, nr, deriv=True)
+        h = 1e-3
+        for d in range(3):
+            vals = []
+            for k in (-2, -1, 1, 2):
+                s = copy.deepcopy(sh)
+                s.center[0, d] += k * h
+                vals.append(r2n_block(s, nr, ld=True))
+            fd = (vals[0] - 8 * vals[1] + 8 * vals[2] - vals[3]) / (12 * h)
+            sc = max(1e-3, np.abs(D[d]).max())
+            assert np.allclose(D[d], fd, atol=1e-9 * sc, rtol=1e-8), (la, lb, nr, d)
+        s = copy.deepcopy(sh)
+        s.center += np.array([0.3, -1.1, 0.7])
+        assert np.allclose(r2n_block(s, nr), V, rtol=1e-12, atol=1e-14 * max(1, np.abs(V).max()))
+
+
+def test_r2n_double_vs_long_double():
+    rng = np.random.default_rng(5)
+    for la, lb, nr in [(4, 4, 5), (3, 0, 2), (0, 4, 1)]:
+        sh = rand_pair(rng, la, lb, K=4, lo=0.1, hi=20, d=2.5)
+        V, D = r2n_block(sh, nr, deriv=True)
+        Vl, Dl = r2n_block(sh, nr, deriv=True, ld=True)
+        assert np.allclose(V, Vl, rtol=1e-12, atol=1e-13 * max(1, np.abs(Vl).max()))
+        assert np.allclose(D, Dl, rtol=1e-12, atol=1e-13 * max(1, np.abs(Dl).max()))
