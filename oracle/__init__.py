@@ -21,10 +21,11 @@ OPS = {"overlap": 0, "coulomb": 1, "erf": 2, "erfc": 3, "gauss": 4,
 _libs: dict = {}
 
 
-def _lib(long_double: bool = False):
-    key = "ld" if long_double else "d"
+def _lib(long_double=False):
+    """long_double: False (double), True (long double) or "quad" (__float128)."""
+    key = "q" if long_double == "quad" else ("ld" if long_double else "d")
     if key not in _libs:
-        path = os.path.join(HERE, "liboracle_ld.so" if long_double else "liboracle.so")
+        path = os.path.join(HERE, {"q": "liboracle_q.so", "ld": "liboracle_ld.so", "d": "liboracle.so"}[key])
         if not os.path.exists(path):
             from . import build as _b
             _b.build()
@@ -112,7 +113,8 @@ def aab(orb, aux, triples, out_off=None, deriv=False, long_double=False):
 
 def r2n(shells, nr: int, pair_idx, out_off=None, deriv=False, long_double=False):
     """(a|r_a^{2n}|b) blocks (Sec. II.C) and, with ``deriv``, d/dR_a (the
-    operator moves with a); layout as in ``pairs``."""
+    operator moves with a); layout as in ``pairs``. ``long_double="quad"``
+    evaluates in __float128."""
     pair_idx = np.ascontiguousarray(pair_idx, np.int32).reshape(-1, 2)
     la = shells.l[pair_idx[:, 0]].astype(np.int64)
     lb = shells.l[pair_idx[:, 1]].astype(np.int64)

@@ -41,7 +41,9 @@
  *     each shell (it does not use the closed-form N_l of eq. N_l).
  *
  * The arithmetic type `real` is double by default and long double when built
- * with -DORACLE_LONG_DOUBLE; the long-double build arbitrates disagreements.
+ * with -DORACLE_LONG_DOUBLE (the arbiter of disagreements) and __float128 with
+ * -DORACLE_QUAD (113-bit significand, for (a|r_a^{2n}|b) at large n, whose
+ * Cartesian expansion cancels beyond what long double resolves).
  */
 #include <math.h>
 #include <stdint.h>
@@ -51,7 +53,16 @@
 #include <omp.h>
 #endif
 
-#ifdef ORACLE_LONG_DOUBLE
+#if defined(ORACLE_QUAD)
+#include <quadmath.h>
+typedef __float128 real;
+#define R_EXP expq
+#define R_SQRT sqrtq
+#define R_ERF erfq
+#define R_FABS fabsq
+#define R_POW powq
+#define R_EPS 1e-34Q
+#elif defined(ORACLE_LONG_DOUBLE)
 typedef long double real;
 #define R_EXP expl
 #define R_SQRT sqrtl
