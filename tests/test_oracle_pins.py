@@ -589,3 +589,15 @@ def test_r2n_double_vs_long_double():
         Vl, Dl = r2n_block(sh, nr, deriv=True, ld=True)
         assert np.allclose(V, Vl, rtol=1e-12, atol=1e-13 * max(1, np.abs(Vl).max()))
         assert np.allclose(D, Dl, rtol=1e-12, atol=1e-13 * max(1, np.abs(Dl).max()))
+
+
+def test_r2n_quad_vs_long_double():
+    """The __float128 build (the arbiter for large n) against the long-double
+    build where the latter is well conditioned (n <= 2, compact exponents)."""
+    rng = np.random.default_rng(8)
+    for la, lb, nr in [(4, 4, 2), (3, 1, 1), (0, 4, 2), (2, 2, 0)]:
+        sh = rand_pair(rng, la, lb, K=3, lo=0.5, hi=5, d=1.7)
+        V, D = r2n_block(sh, nr, deriv=True, ld=True)
+        Vq, Dq = r2n_block(sh, nr, deriv=True, ld="quad")
+        assert np.allclose(V, Vq, rtol=1e-15, atol=1e-16 * max(1, np.abs(Vq).max()))
+        assert np.allclose(D, Dq, rtol=1e-14, atol=1e-15 * max(1, np.abs(Dq).max()))
