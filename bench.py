@@ -349,6 +349,18 @@ def main():
                         "hbm_frac": round(b3 / (ms3 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         del o3, d3
         torch.cuda.synchronize()
+        log("r_a^2n two-center integrals")
+        b_r2n = int(workmodel.workload_bytes(w, True))
+        r2n = {"workload": "five_ops500 pair list (all shell pairs of the 500-atom workload), values + d/dR_a",
+               "pairs": n, "alg_bytes_per_call": b_r2n}
+        steps5 = max(2, args.steps // 3)
+        for nr in (1, 3, 5):
+            ms5, _ = timed(eng, lambda: eng.pairs_r2n(dsh, nr, pairs, out_off, outs[ops[0]], douts[ops[0]]),
+                           steps5, 1)
+            r2n[f"n{nr}"] = {"ms_per_call": round(ms5, 4), "blocks_per_s": round(n / (ms5 / 1e3), 1),
+                             "hbm_frac": round(b_r2n / (ms5 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        extra["r2n"] = r2n
+        torch.cuda.synchronize()
         log("uneven molecules")
         w4 = inputs.molecules256(n_mol=32)
         off4, tot4 = w4.out_offsets()

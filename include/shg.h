@@ -97,6 +97,16 @@ int shg_pairs_deriv(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
                     const int32_t *pairs, int64_t n, const int64_t *out_off,
                     double *out, double *dout);
 
+/* (a|r_a^{2n}|b) (Sec. II.C, eq. ara2nb_def, evaluated by eqs. ara2nb and
+ * T_rab2_deriv): the local operator r_a^{2n} = |r - R_a|^{2n} centred on a's
+ * center, 0 <= nr <= 5 (else SHG_EINVAL; nr = 0 is the overlap).
+ *   pairs, out_off, out as in shg_pairs (a and b from the same shell table)
+ *   dout    nullable; d/dR_a with a and the operator moving together, x, y, z
+ *           blocks at dout[3*out_off[i]]
+ * Shells as in shg_pairs. */
+int shg_pairs_r2n(shg_ctx *ctx, const shg_shells *sh, int nr, const int32_t *pairs,
+                  int64_t n, const int64_t *out_off, double *out, double *dout);
+
 /* Three-index overlap (a b a~) (Sec. II.D, eq. aba_integrals): a = orb shell
  * t[0] and a~ = aux shell t[1] share center A (their centers must be equal
  * bit for bit, else SHG_EINVAL), b = orb shell t[2].

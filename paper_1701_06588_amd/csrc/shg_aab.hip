@@ -398,6 +398,7 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
             ta.out = c->Yv[it.w];
             ta.dout = deriv ? c->Yd[it.w] : nullptr;
             ta.triples = triples;
+            ta.tstride = 3;
             ta.P = c->Pbuf[it.w];
             ta.pstride = AAB_PSTRIDE;
             ta.poff = iL * 8;

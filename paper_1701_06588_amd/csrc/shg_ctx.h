@@ -110,6 +110,8 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int n);
 __global__ void k_prep_shells(int nshell, const int32_t *l, const int32_t *nprim, const int64_t *prim_off,
                               const double *exps, const double *coefs, int64_t nprim_total, int lmax, double *w,
                               int32_t *err);
+__global__ void k_classify(int64_t n, const int32_t *pairs, int nshell, const int32_t *l, const int32_t *nprim,
+                           int32_t *keys, int32_t *hist, int32_t *err);
 __global__ void k_scan_bins(const int32_t *hist, int nb, int32_t *starts, int32_t *cursor);
 __global__ void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor, int32_t *order, const int32_t *pairs,
                           const int64_t *out_off, PairRec *rec);

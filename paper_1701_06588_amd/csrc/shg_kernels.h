@@ -50,14 +50,18 @@ struct TileArgs {
     double *out, *dout;
     double omega;
     int op;
-    // three-index overlap mode (triples != nullptr): items are (a, a~, b)
-    // triples; phase 1 loads O^(k) = P^(k)_La from P[(pos - ybase) * pstride +
-    // poff + k] and block `pos` goes to out[(pos - ybase) * ys + yoff] (scratch
-    // Y blocks of one chunk of a triple class)
+    // precomputed-monopole mode (triples != nullptr): items are rows of
+    // `tstride` shell indices, a first and b last ((a, a~, b) triples of the
+    // three-index overlap, (a, b) pairs of (a|r_a^{2n}|b)); phase 1 loads
+    // O^(k) from P[(pos - ybase) * pstride + poff + k] and block `pos` goes to
+    // out[ooff[item]] when ooff is set, else to out[(pos - ybase) * ys + yoff]
+    // (scratch Y blocks of one chunk of a triple class)
     const int32_t *triples;
     const double *P;
     int pstride, poff;
     int64_t ybase, ys, yoff;
+    const int64_t *ooff;
+    int tstride;
 };
 
 // tile shape: TP pairs (64, 128 or 256) and rows_pp block rows per LDS pass
@@ -163,17 +167,19 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
     // ---- phase 1: radial terms and contraction, G lanes per shell pair ----
     // (classes with l_a > LMAX only occur as L_a blocks of the three-index overlap)
     if (LA > LMAX || a.triples) {
-        // (a b a~) mode: O^(k) = P^(k)_La was computed per triple by k_aab_radial
+        // precomputed mode: O^(k) = P^(k)_La of a triple (k_aab_radial) or T^(k)
+        // of a pair under r_a^{2n} (k_r2n_radial)
         for (int i = tid; i < tcount; i += TILE_THREADS) {
             const int64_t pos = tstart + i;
 #pragma unroll
             for (int k = 0; k < PK::NK; ++k)
                 sO[i * SO_STRIDE + k] = a.P[(pos - a.ybase) * a.pstride + a.poff + k];
             const int p = a.order[pos];
-            const int sa = a.triples[3 * (int64_t)p], sb = a.triples[3 * (int64_t)p + 2];
+            const int64_t row = (int64_t)a.tstride * p;
+            const int sa = a.triples[row], sb = a.triples[row + a.tstride - 1];
 #pragma unroll
             for (int d = 0; d < 3; ++d) sO[i * SO_STRIDE + 6 + d] = a.center[3 * sa + d] - a.center[3 * sb + d];
-            const int64_t off = (pos - a.ybase) * a.ys + a.yoff;
+            const int64_t off = a.ooff ? a.ooff[p] : (pos - a.ybase) * a.ys + a.yoff;
             sPv[i] = a.out + off;
             sPd[i] = a.dout ? a.dout + 3 * off : nullptr;
         }

@@ -62,6 +62,8 @@ def load_library(path: str = LIB_PATH):
     lib.shg_pairs_deriv.restype = C.c_int
     lib.shg_aab.argtypes = [P, C.POINTER(ShgShells), C.POINTER(ShgShells), P, C.c_int64, P, P, P]
     lib.shg_aab.restype = C.c_int
+    lib.shg_pairs_r2n.argtypes = [P, C.POINTER(ShgShells), C.c_int, P, C.c_int64, P, P, P]
+    lib.shg_pairs_r2n.restype = C.c_int
     I = C.c_int
     lib.shg_set_tile_shape.argtypes = [P, I, I, I, I, I, I]
     lib.shg_get_tile_shape.argtypes = [P, I, I, I, I, C.POINTER(I), C.POINTER(I)]
@@ -201,6 +203,13 @@ class Engine:
         else:
             rc = self.lib.shg_pairs_deriv(self.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs), n,
                                           _ptr(out_off), _ptr(out), _ptr(dout))
+        self._check(rc)
+
+    def pairs_r2n(self, dsh: DeviceShells, nr: int, pairs, out_off, out, dout=None):
+        """shg_pairs_r2n: (a|r_a^{2n}|b) (and d/dR_a with `dout`) on device tensors."""
+        n = int(pairs.shape[0])
+        rc = self.lib.shg_pairs_r2n(self.ctx, C.byref(dsh.c), int(nr), _ptr(pairs), n, _ptr(out_off), _ptr(out),
+                                    _ptr(dout))
         self._check(rc)
 
     def aab(self, orb: DeviceShells, aux: DeviceShells, triples, out_off, out, dout=None):

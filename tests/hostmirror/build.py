@@ -10,7 +10,7 @@ OUT_DIR = os.path.join(ROOT, "tests", "_build")
 LIB = os.path.join(OUT_DIR, "libshg_hostmirror.so")
 # clang compiles these template-heavy sources several times faster than g++
 CXX = "/opt/rocm/llvm/bin/clang++" if os.path.exists("/opt/rocm/llvm/bin/clang++") else "g++"
-DEPS = [os.path.join(ROOT, "paper_1701_06588_amd", "csrc", f) for f in ("shg_math.h", "boys_table.h")]
+DEPS = [os.path.join(ROOT, "paper_1701_06588_amd", "csrc", f) for f in ("shg_math.h", "shg_r2n_math.h", "boys_table.h")]
 
 
 def _stale() -> bool:

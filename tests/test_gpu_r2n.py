@@ -1,0 +1,124 @@
+"""GPU parity of shg_pairs_r2n ((a|r_a^{2n}|b), Sec. II.C, and d/dR_a) through
+the C ABI against the CPU oracle in __float128, element by element (the
+oracle's Cartesian expansion of r_a^{2n} cancels beyond what long double
+resolves at n >= 3 with diffuse exponents)."""
+import numpy as np
+import pytest
+
+import oracle
+from parity import assert_parity
+from paper_1701_06588_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def engine():
+    from paper_1701_06588_amd import shg
+    e = shg.Engine()
+    yield e
+    e.close()
+
+
+def run_r2n(engine, w, nr, deriv, pairs=None):
+    import torch
+    dev = torch.device("cuda")
+    dsh = engine.shells(w.shells)
+    pr = w.pairs if pairs is None else pairs
+    la = w.shells.l[pr[:, 0]].astype(np.int64)
+    lb = w.shells.l[pr[:, 1]].astype(np.int64)
+    sz = (2 * la + 1) * (2 * lb + 1)
+    off = np.zeros(len(sz), np.int64)
+    off[1:] = np.cumsum(sz[:-1])
+    tot = int(sz.sum())
+    p = torch.as_tensor(np.ascontiguousarray(pr, np.int32), device=dev)
+    oo = torch.as_tensor(off, device=dev)
+    out = torch.full((max(tot, 1),), float("nan"), dtype=torch.float64, device=dev)
+    dout = torch.full((max(3 * tot, 1),), float("nan"), dtype=torch.float64, device=dev) if deriv else None
+    engine.pairs_r2n(dsh, nr, p, oo, out, dout)
+    torch.cuda.synchronize()
+    return off, sz, out.cpu().numpy()[:tot], (dout.cpu().numpy()[:3 * tot] if deriv else None)
+
+
+_W = {}
+
+
+def small():
+    if "w" not in _W:
+        _W["w"] = inputs.small_pairs(2026, 2500)
+    return _W["w"]
+
+
+@pytest.mark.parametrize("nr", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("deriv", [False, True])
+def test_r2n_all_classes_random(engine, nr, deriv):
+    """2500 random pairs: every (la, lb) class with l <= 4, K in 1..7, exponents
+    [0.05, 50]; several tiles per class with a ragged tail."""
+    w = small()
+    print(f"case r2n small2500 n={nr} deriv={deriv}", flush=True)
+    off, sz, out, dout = run_r2n(engine, w, nr, deriv)
+    if deriv:
+        ro, rd = oracle.r2n(w.shells, nr, w.pairs, off, deriv=True, long_double="quad")
+        assert_parity(dout, rd, off, sz, True, f"r2n n={nr} d/dR_a")
+    else:
+        ro = oracle.r2n(w.shells, nr, w.pairs, off, long_double="quad")
+    assert_parity(out, ro, off, sz, False, f"r2n n={nr}")
+
+
+def test_r2n_zero_matches_overlap_path(engine):
+    """n = 0 is the overlap: the r_a^{2n} route (monopole T^(k) from the
+    (0|r^0|0) integrals) against the two-center overlap route."""
+    from paper_1701_06588_amd import shg
+    w = small()
+    print("case r2n n=0 vs shg_pairs_deriv overlap", flush=True)
+    off, sz, out, dout = run_r2n(engine, w, 0, True)
+    so, sd = shg.run_workload_pairs(engine, w, "overlap", True)
+    assert_parity(out, so, off, sz, False, "n=0 vs overlap")
+    assert_parity(dout, sd, off, sz, True, "n=0 vs overlap d/dR_a")
+
+
+def test_r2n_deterministic_and_edges(engine):
+    import torch
+    from paper_1701_06588_amd import shg
+    w = small()
+    print("case r2n determinism and edge cases", flush=True)
+    a = run_r2n(engine, w, 3, True)
+    b = run_r2n(engine, w, 3, True)
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+    dev = torch.device("cuda")
+    dsh = engine.shells(w.shells)
+    empty_p = torch.zeros((0, 2), dtype=torch.int32, device=dev)
+    empty_o = torch.zeros(0, dtype=torch.int64, device=dev)
+    out = torch.zeros(4, dtype=torch.float64, device=dev)
+    engine.pairs_r2n(dsh, 2, empty_p, empty_o, out)
+    assert torch.all(out == 0)
+    one_p = torch.zeros((1, 2), dtype=torch.int32, device=dev)
+    one_o = torch.zeros(1, dtype=torch.int64, device=dev)
+    big = torch.zeros(81 * 4, dtype=torch.float64, device=dev)
+    for bad_n in (-1, 6):
+        with pytest.raises(shg.ShgError):
+            engine.pairs_r2n(dsh, bad_n, one_p, one_o, big)
+    bad = torch.tensor([[0, w.shells.n]], dtype=torch.int32, device=dev)
+    with pytest.raises(shg.ShgError):
+        engine.pairs_r2n(dsh, 1, bad, one_o, big)
+    # the context stays usable after an error
+    c = run_r2n(engine, w, 3, True)
+    assert np.array_equal(a[2], c[2])
+
+
+def test_r2n_full_five_ops500_sampled(engine):
+    """The full 500-atom pair list (~1.6e6 pairs, values + d/dR_a, n = 5) in
+    one call; 1500 sampled blocks against the oracle."""
+    w = inputs.five_ops500()
+    print(f"case r2n five_ops500 n=5 pairs={len(w.pairs)}", flush=True)
+    off, sz, out, dout = run_r2n(engine, w, 5, True)
+    assert np.all(np.isfinite(out)) and np.all(np.isfinite(dout))
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(len(w.pairs), 1500, replace=False))
+    sub_off = np.zeros(len(idx), np.int64)
+    sub_off[1:] = np.cumsum(sz[idx][:-1])
+    ro, rd = oracle.r2n(w.shells, 5, w.pairs[idx], sub_off, deriv=True, long_double="quad")
+    got = np.concatenate([out[off[i]:off[i] + sz[i]] for i in idx])
+    gotd = np.concatenate([dout[3 * off[i]:3 * off[i] + 3 * sz[i]] for i in idx])
+    assert_parity(got, ro, sub_off, sz[idx], False, "r2n five_ops500")
+    assert_parity(gotd, rd, sub_off, sz[idx], True, "r2n five_ops500 d/dR_a")

@@ -22,6 +22,7 @@ def hm():
     P = C.c_void_p
     lib.shgm_pairs.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int, C.c_double, P, C.c_int64, P, P, P]
     lib.shgm_boys.argtypes = [C.c_int, C.c_double, P]
+    lib.shgm_r2n.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int, P, C.c_int64, P, P, P]
     return lib
 
 
@@ -63,3 +64,20 @@ def test_host_mirror_boys_vs_mpmath(hm):
                    mpmath.gammainc(n + 0.5, 0, T) / (2 * mpmath.mpf(T) ** (n + 0.5)))
             worst = max(worst, abs(F[n] - float(ref)) / float(ref))
     assert worst < 2e-14, worst
+
+
+@pytest.mark.parametrize("nr", [0, 1, 2, 3, 4, 5])
+def test_host_mirror_r2n_vs_oracle(hm, nr):
+    """(a|r_a^{2n}|b): the engine's double-double monopole T^(k) and block
+    assembly on the CPU against the __float128 oracle, every (la, lb) class."""
+    w = inputs.small_pairs(2026, 800)
+    sh = w.shells
+    off, tot = w.out_offsets()
+    sz = w.block_sizes()
+    out, dout = np.zeros(tot), np.zeros(3 * tot)
+    rc = hm.shgm_r2n(sh.n, _p(sh.center), _p(sh.l), _p(sh.nprim), _p(sh.prim_off), _p(sh.exps), _p(sh.coefs),
+                     nr, _p(np.ascontiguousarray(w.pairs)), len(w.pairs), _p(off), _p(out), _p(dout))
+    assert rc == 0
+    ro, rd = oracle.r2n(sh, nr, w.pairs, off, deriv=True, long_double="quad")
+    assert_parity(out, ro, off, sz, False, f"r2n n={nr}")
+    assert_parity(dout, rd, off, sz, True, f"r2n n={nr} d/dR_a")
