@@ -16,7 +16,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 OPS = {"overlap": 0, "coulomb": 1, "erf": 2, "erfc": 3, "gauss": 4,
-       "overlap_vrr": 5}  # overlap through the generic recurrence (self-check only)
+       "overlap_vrr": 5,  # overlap through the generic recurrence (self-check only)
+       "gcoulomb": 6}     # exp(-w r^2)/r
 
 _libs: dict = {}
 

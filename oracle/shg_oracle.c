@@ -21,7 +21,8 @@
  *     x_A^i y_A^j z_A^k exp(-alpha r_A^2):
  *       - overlap: the one-dimensional Obara-Saika recurrence, separately per
  *         Cartesian direction (Sec. III notes the overlap recursion separates);
- *       - the non-local operators 1/r, erf(wr)/r, erfc(wr)/r, exp(-wr^2): an
+ *       - the non-local operators 1/r, erf(wr)/r, erfc(wr)/r, exp(-wr^2) and
+ *         exp(-wr^2)/r: an
  *         Obara-Saika style vertical recurrence on an auxiliary index n, where
  *         [0|0]^(n) is the n-th derivative of the s-s integral with respect to
  *         R_ab^2 (Table S1 of the supplement);
@@ -83,7 +84,8 @@ typedef double real;
 static const real PI_R = 3.141592653589793238462643383279502884L;
 
 enum { OP_OVERLAP = 0, OP_COULOMB = 1, OP_ERF = 2, OP_ERFC = 3, OP_GAUSS = 4,
-       OP_OVERLAP_VRR = 5 /* overlap through the generic recurrence (self-check) */ };
+       OP_OVERLAP_VRR = 5 /* overlap through the generic recurrence (self-check) */,
+       OP_GCOULOMB = 6 /* exp(-w r^2)/r */ };
 
 #define LCART_MAX 12   /* largest Cartesian degree handled (l_a + l_a~ + 1 <= 10) */
 #define NMAX_AUX 16    /* largest auxiliary index of the vertical recurrence */
@@ -148,6 +150,23 @@ static void ss_derivs(int op, real w, real a, real b, real R2, int nmax, real *g
             g[n] = (op == OP_ERF) ? v : pre * f * F[n] - v;
             f *= -rho;
             f2 *= -rho * s;
+        }
+        break;
+    }
+    case OP_GCOULOMB: {
+        /* e^{-w T/q} F_0(rho T/q) times a constant (Table S1); its n-th R^2
+         * derivative by the Leibniz rule, with d/dx F_j = -F_{j+1} */
+        real q = rho + w, x = rho * T / q;
+        real pre = R_POW(PI_R / p, (real)1.5) * 2 * PI_R / q * R_EXP(-w * T / q);
+        real ea = -w * rho / q, fb = -rho * rho / q;
+        boys(nmax, x, F);
+        for (int n = 0; n <= nmax; ++n) {
+            real acc = 0, c = 1;   /* binom(n, j) */
+            for (int j = 0; j <= n; ++j) {
+                acc += c * R_POW(ea, (real)(n - j)) * R_POW(fb, (real)j) * F[j];
+                c = c * (n - j) / (j + 1);
+            }
+            g[n] = pre * acc;
         }
         break;
     }
@@ -604,7 +623,7 @@ int shgo_pairs(int32_t nshell, const double *center, const int32_t *l, const int
                double omega, const int32_t *pairs, int64_t n, const int64_t *out_off, double *out,
                double *dout)
 {
-    if (n < 0 || op < 0 || op > 5) return -1;
+    if (n < 0 || op < 0 || op > 6) return -1;
     if (n == 0) return 0;
     if (check_shells(nshell, l, nprim, 8)) return -1;
     shells_t sh = {center, l, nprim, prim_off, exps, coefs};

@@ -88,4 +88,13 @@ def potential_s(op, omega, beta, d):
         return potential_s("coulomb", omega, beta, d) - potential_s("erf", omega, beta, d)
     if op == "gauss":
         return (pi / (beta + omega)) ** 1.5 * np.exp(-beta * omega * d * d / (beta + omega))
+    if op == "gcoulomb":
+        # exp(-w s^2)/s = (2/sqrt(pi)) int_0^inf exp(-(t^2 + w) s^2) dt; the Gaussian convolution
+        # under the integral and t = sqrt(beta + w) tan(phi), sin(phi) = u, give
+        # 2 pi / (beta + w) exp(-beta w d^2 / (beta + w)) int_0^1 exp(-x u^2) du,
+        # x = beta^2 d^2 / (beta + w), and int_0^1 exp(-x u^2) du = sqrt(pi) erf(sqrt x) / (2 sqrt x)
+        x = beta * beta * d * d / (beta + omega)
+        sx = np.sqrt(np.maximum(x, 1e-300))
+        f0 = np.where(x < 1e-12, 1.0 - x / 3, sqrt(pi) * erf(sx) / (2 * sx))
+        return 2 * pi / (beta + omega) * np.exp(-beta * omega * d * d / (beta + omega)) * f0
     raise ValueError(op)

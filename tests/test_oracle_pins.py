@@ -15,9 +15,9 @@ import oracle
 import pointwise as pw
 from paper_1701_06588_amd import inputs
 
-OPS = ("overlap", "coulomb", "erf", "erfc", "gauss")
+OPS = ("overlap", "coulomb", "erf", "erfc", "gauss", "gcoulomb")
 OMEGA = {"overlap": 0.0, "coulomb": 0.0, "erf": 0.33, "erfc": 0.11, "gauss": 1.0,
-         "overlap_vrr": 0.0}
+         "overlap_vrr": 0.0, "gcoulomb": 0.7}
 
 
 def one_pair(la, lb, ea, ca, eb, cb, A, B):
@@ -213,7 +213,7 @@ def test_overlap_vs_quadrature(la, lb):
     assert np.allclose(S, ref, atol=1e-11 * max(1, np.abs(ref).max())), np.abs(S - ref).max()
 
 
-@pytest.mark.parametrize("op", ["coulomb", "erf", "erfc", "gauss"])
+@pytest.mark.parametrize("op", ["coulomb", "erf", "erfc", "gauss", "gcoulomb"])
 @pytest.mark.parametrize("la", [0, 1, 2, 3])
 def test_nonlocal_a_s_vs_quadrature(op, la):
     """(a|O|s_b) against quadrature of phi_a times the analytic potential of the
@@ -601,3 +601,21 @@ def test_r2n_quad_vs_long_double():
         Vq, Dq = r2n_block(sh, nr, deriv=True, ld="quad")
         assert np.allclose(V, Vq, rtol=1e-15, atol=1e-16 * max(1, np.abs(Vq).max()))
         assert np.allclose(D, Dq, rtol=1e-14, atol=1e-15 * max(1, np.abs(Dq).max()))
+
+
+def test_gcoulomb_limits():
+    """exp(-w r^2)/r: w -> 0 gives the Coulomb blocks; the damped kernel is
+    bounded by 1/r, so for s functions (positive integrands) the damped block
+    lies strictly between 0 and the Coulomb one."""
+    rng = np.random.default_rng(44)
+    for la, lb in [(0, 0), (2, 1), (3, 3), (4, 2)]:
+        sh = rand_pair(rng, la, lb, K=3)
+        C, DC = block(sh, "coulomb", deriv=True)
+        G, DG = oracle.pairs(sh, "gcoulomb", 1e-13, np.array([[0, 1]]), deriv=True, long_double=True)
+        assert np.allclose(G.reshape(C.shape), C, rtol=1e-11, atol=1e-13 * max(1, np.abs(C).max()))
+        assert np.allclose(DG.reshape(DC.shape), DC, rtol=1e-10, atol=1e-12 * max(1, np.abs(DC).max()))
+    sh = rand_pair(rng, 0, 0, K=2)
+    c = block(sh, "coulomb")[0, 0]
+    for w in (0.1, 1.0, 10.0):
+        g = oracle.pairs(sh, "gcoulomb", w, np.array([[0, 1]]))[0]
+        assert 0 < g < c
