@@ -52,7 +52,10 @@ typedef enum {
     SHG_COULOMB = 1,   /* 1/r                            omega ignored */
     SHG_ERF     = 2,   /* erf(omega r)/r   (long range)   omega > 0    */
     SHG_ERFC    = 3,   /* erfc(omega r)/r  (short range)  omega > 0    */
-    SHG_GAUSS   = 4    /* exp(-omega r^2)                 omega > 0    */
+    SHG_GAUSS   = 4,   /* exp(-omega r^2)                 omega > 0    */
+    SHG_GCOULOMB = 5   /* exp(-omega r^2)/r               omega > 0;
+                          shg_pairs / shg_pairs_deriv only (not in plans,
+                          screening or tuning calls) */
 } shg_op;
 
 /* Shell table. All arrays are DEVICE arrays of length nshell (prim arrays of

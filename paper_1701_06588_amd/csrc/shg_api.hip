@@ -349,12 +349,23 @@ static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omeg
 extern "C" int shg_pairs(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
                          const int64_t *out_off, double *out)
 {
+    if (c && op == SHG_GCOULOMB) {
+        if (!(omega > 0.0 && omega < 1e300))
+            return set_err(c, SHG_EINVAL, "shg_pairs: omega must be positive and finite for this operator");
+        return gcoulomb_pairs(c, "shg_pairs", omega, sh, pairs, n, out_off, out, nullptr);
+    }
     return pairs_common(c, sh, op, omega, pairs, n, out_off, out, nullptr, false);
 }
 
 extern "C" int shg_pairs_deriv(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
                                int64_t n, const int64_t *out_off, double *out, double *dout)
 {
+    if (c && op == SHG_GCOULOMB) {
+        if (!(omega > 0.0 && omega < 1e300))
+            return set_err(c, SHG_EINVAL, "shg_pairs_deriv: omega must be positive and finite for this operator");
+        if (!dout) return set_err(c, SHG_EINVAL, "shg_pairs_deriv: NULL pointer argument");
+        return gcoulomb_pairs(c, "shg_pairs_deriv", omega, sh, pairs, n, out_off, out, dout);
+    }
     return pairs_common(c, sh, op, omega, pairs, n, out_off, out, dout, true);
 }
 

@@ -197,6 +197,8 @@ extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, doub
 {
     if (!c || !plan) return SHG_EINVAL;
     *plan = nullptr;
+    if ((int)op < 0 || (int)op > 4)
+        return set_err(c, SHG_EINVAL, "shg_plan_create: operator %d is not available in plans", (int)op);
     const bool deriv = dout != nullptr;
     // evaluate once through the plain path: validates the input and bins the pairs
     int rc = deriv ? shg_pairs_deriv(c, sh, op, omega, pairs, n, out_off, out, dout)
@@ -356,6 +358,9 @@ extern "C" int shg_plan_create_multi(shg_ctx *c, const shg_shells *sh, int nops,
     const bool deriv = douts != nullptr;
     for (int o = 0; o < nops; ++o)
         if (!outs[o] || (deriv && !douts[o])) return set_err(c, SHG_EINVAL, "%s: NULL output pointer", what);
+    for (int o = 0; o < nops; ++o)
+        if ((int)ops[o] < 0 || (int)ops[o] > 4)
+            return set_err(c, SHG_EINVAL, "%s: operator %d is not available in plans", what, (int)ops[o]);
     // every operator once through the plain path: validation and the exact blocks
     int rc = 0;
     for (int o = 0; o < nops; ++o) {

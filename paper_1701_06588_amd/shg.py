@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libshg.so")
 
-OPS = {"overlap": 0, "coulomb": 1, "erf": 2, "erfc": 3, "gauss": 4}
+OPS = {"overlap": 0, "coulomb": 1, "erf": 2, "erfc": 3, "gauss": 4, "gcoulomb": 5}
 ERRORS = {-1: "SHG_EINVAL", -2: "SHG_ENOMEM", -3: "SHG_EDEVICE"}
 EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pairs_deriv", "shg_aab",
            "shg_set_tile_shape", "shg_get_tile_shape", "shg_autotune", "shg_tuning_save", "shg_tuning_load",
