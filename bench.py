@@ -6,7 +6,7 @@ within 12 bohr (1.61e6 shell pairs), evaluated for all five operators (overlap,
 Coulomb, erfc(0.11 r)/r, erf(0.33 r)/r, exp(-r^2)) with values and d/dR_a.
 Inputs are synthetic (seeded) and resident in HBM before the timed region.
 
-Three paths over the same pair lists, each timed with HIP events on the
+Four paths over the same pair lists, each timed with HIP events on the
 library stream over --steps steps after --warmup untimed ones:
   plain             shg_pairs_deriv per operator (binning + one launch per class)
   batched           one recorded plan per operator (binned once, hipGraph replay,
@@ -14,6 +14,10 @@ library stream over --steps steps after --warmup untimed ones:
   batched+screened  the same with screening: pairs whose analytic bound (covering
                     values and d/dR_a) is below tau_blk = 1e-10 / N_candidates are
                     skipped (blocks zeroed once when the plan is made)
+  batched+screened+swap  screened plans over the pairs with a <= b only; the
+                    (b, a) blocks are filled by shg_pairs_swap (transpose, and
+                    minus the transpose for d/dR, Sec. V); audited element-wise
+                    against the plain path
 `value` is the batched+screened rate in candidate blocks per second (every
 block of the step counts, skipped or not). Kept blocks are checked bitwise
 against the plain path; the missed mass is exact (L1 of the plain path's values
@@ -135,7 +139,7 @@ def main():
                     help="skip the three-index overlap and uneven-molecules measurements")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB first (calibrates HBM byte counters)")
-    ap.add_argument("--paths", default="plain,batched,screened",
+    ap.add_argument("--paths", default="plain,batched,screened,swap",
                     help="comma list of paths to run (the value needs 'screened')")
     args = ap.parse_args()
 
@@ -238,6 +242,62 @@ def main():
                       "missed_mass": m_tot, "missed_mass_deriv": dm_tot, "kept_blocks_bitwise_equal": bad == 0,
                       "kept_max_diff_rel_to_max": worst,
                       "audit": "every skipped block evaluated exactly (plain path), L1 of its elements"})
+
+    # ---- batched + screened + swap symmetry: evaluate a <= b, fill (b, a) by transposition ----
+    a_, b_ = w.pairs[:, 0].astype(np.int64), w.pairs[:, 1].astype(np.int64)
+    nsh = int(w.shells.n)
+    key = a_ * nsh + b_
+    kord = np.argsort(key)
+    mir = np.nonzero(a_ > b_)[0]
+    pos = np.searchsorted(key[kord], b_[mir] * nsh + a_[mir])
+    pos = np.minimum(pos, n - 1)
+    partner = kord[pos]
+    if "swap" in paths and len(mir) and np.all(key[partner] == b_[mir] * nsh + a_[mir]):
+        log("batched+screened+swap path")
+        ci = np.nonzero(a_ <= b_)[0]
+        cpairs = torch.as_tensor(np.ascontiguousarray(w.pairs[ci], np.int32), device=dev)
+        coff = torch.as_tensor(off[ci], device=dev)
+        sw_p = torch.as_tensor(np.ascontiguousarray(w.pairs[partner], np.int32), device=dev)
+        sw_src = torch.as_tensor(off[partner], device=dev)
+        sw_dst = torch.as_tensor(off[mir], device=dev)
+        xouts = {op: torch.zeros(tot, dtype=torch.float64, device=dev) for op in ops}
+        xdouts = {op: torch.zeros(3 * tot, dtype=torch.float64, device=dev) for op in ops}
+        xplans = [shg.Plan(eng, dsh, op, w.omega[op], cpairs, coff, xouts[op], xdouts[op], tau=tau) for op in ops]
+        for p in xplans:
+            p.autotune(3)
+
+        def step_swap():
+            for op, p in zip(ops, xplans):
+                p.execute()
+                eng.pairs_swap(dsh, sw_p, sw_src, sw_dst, xouts[op], xdouts[op])
+
+        step_swap()
+        eng._check(eng.lib.shg_pairs_swap_check(eng.ctx))
+        ms_x, _ = timed(eng, step_swap, args.steps, args.warmup)
+        ms_xp, _ = timed(eng, lambda: [p.execute() for p in xplans], args.steps, args.warmup)
+        # audit: every element against the plain path, |x - r| <= 1e-12 |r| + 1e-14 max(1, max|r|)
+        # per operator and component; skipped blocks (both orders) as missed mass
+        xbad, xworst, xm, xdm = 0, 0.0, 0.0, 0.0
+        for op in ops:
+            for x_, r_ in ((xouts[op], outs[op]), (xdouts[op], douts[op])):
+                kept = x_ != 0
+                tol = 1e-12 * r_.abs() + 1e-14 * max(1.0, r_.abs().max().item())
+                xbad += int((((x_ - r_).abs() > tol) & kept).sum().item())
+                xworst = max(xworst, float(((x_ - r_).abs() * kept).max().item() / max(r_.abs().max().item(), 1e-300)))
+            xm += float(outs[op][xouts[op] == 0].abs().sum().item())
+            xdm += float(douts[op][xdouts[op] == 0].abs().sum().item())
+        res_paths["batched+screened+swap"] = {
+            "blocks_per_s": round(blocks_per_step / (ms_x / 1e3), 1), "ms_per_step": round(ms_x, 4),
+            "evaluated_pairs": int(len(ci)), "swapped_pairs": int(len(mir)),
+            "plans_ms_per_step": round(ms_xp, 4), "swaps_ms_per_step": round(ms_x - ms_xp, 4),
+            "kept_within_tol": xbad == 0, "kept_max_diff_rel_to_max": xworst,
+            "missed_mass": xm, "missed_mass_deriv": xdm,
+            "note": "screened plans over the pairs with a <= b; the (b, a) blocks by shg_pairs_swap "
+                    "(transpose; minus the transpose for d/dR); audited element-wise against the plain path"}
+        for p in xplans:
+            p.close()
+        del xouts, xdouts
+        torch.cuda.synchronize()
 
     # ---- roofline of the dominant kernel of the value path ----
     per = []

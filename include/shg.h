@@ -110,6 +110,19 @@ int shg_pairs_deriv(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
 int shg_pairs_r2n(shg_ctx *ctx, const shg_shells *sh, int nr, const int32_t *pairs,
                   int64_t n, const int64_t *out_off, double *out, double *dout);
 
+/* Swap symmetry (Sec. V): for the operators of shg_op (even functions of
+ * r1 - r2) and each function keeping its center, (b|O|a) = (a|O|b)^T, and by
+ * translation invariance d/dR_b (b|O|a) = -(d/dR_a (a|O|b))^T. Given the
+ * blocks of the pairs (a, b) = pairs[i] already in out (and dout) at
+ * src_off[i], writes the blocks of the swapped pairs (b, a) at dst_off[i] of
+ * the same buffers: (2lb+1) x (2la+1) row-major, derivatives x, y, z at
+ * dout[3*dst_off[i]]; dout nullable. Source and destination blocks must not
+ * overlap. Asynchronous: a pair index or l outside range skips that block and
+ * is reported by shg_pairs_swap_check (which synchronises the stream). */
+int shg_pairs_swap(shg_ctx *ctx, const shg_shells *sh, const int32_t *pairs, int64_t n,
+                   const int64_t *src_off, const int64_t *dst_off, double *out, double *dout);
+int shg_pairs_swap_check(shg_ctx *ctx);
+
 /* Three-index overlap (a b a~) (Sec. II.D, eq. aba_integrals): a = orb shell
  * t[0] and a~ = aux shell t[1] share center A (their centers must be equal
  * bit for bit, else SHG_EINVAL), b = orb shell t[2].

@@ -64,6 +64,10 @@ def load_library(path: str = LIB_PATH):
     lib.shg_aab.restype = C.c_int
     lib.shg_pairs_r2n.argtypes = [P, C.POINTER(ShgShells), C.c_int, P, C.c_int64, P, P, P]
     lib.shg_pairs_r2n.restype = C.c_int
+    lib.shg_pairs_swap.argtypes = [P, C.POINTER(ShgShells), P, C.c_int64, P, P, P, P]
+    lib.shg_pairs_swap.restype = C.c_int
+    lib.shg_pairs_swap_check.argtypes = [P]
+    lib.shg_pairs_swap_check.restype = C.c_int
     I = C.c_int
     lib.shg_set_tile_shape.argtypes = [P, I, I, I, I, I, I]
     lib.shg_get_tile_shape.argtypes = [P, I, I, I, I, C.POINTER(I), C.POINTER(I)]
@@ -211,6 +215,14 @@ class Engine:
         rc = self.lib.shg_pairs_r2n(self.ctx, C.byref(dsh.c), int(nr), _ptr(pairs), n, _ptr(out_off), _ptr(out),
                                     _ptr(dout))
         self._check(rc)
+
+    def pairs_swap(self, dsh: DeviceShells, pairs, src_off, dst_off, out, dout=None, check=False):
+        """shg_pairs_swap: blocks of the swapped pairs (b, a) from those of pairs (a, b)."""
+        n = int(pairs.shape[0])
+        self._check(self.lib.shg_pairs_swap(self.ctx, C.byref(dsh.c), _ptr(pairs), n, _ptr(src_off), _ptr(dst_off),
+                                            _ptr(out), _ptr(dout)))
+        if check:
+            self._check(self.lib.shg_pairs_swap_check(self.ctx))
 
     def aab(self, orb: DeviceShells, aux: DeviceShells, triples, out_off, out, dout=None):
         n = int(triples.shape[0])
