@@ -139,6 +139,7 @@ def main():
                     help="skip the three-index overlap and uneven-molecules measurements")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB first (calibrates HBM byte counters)")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the copy / FP64 ceiling measurement")
     ap.add_argument("--paths", default="plain,batched,screened,swap",
                     help="comma list of paths to run (the value needs 'screened')")
     args = ap.parse_args()
@@ -299,6 +300,30 @@ def main():
         del xouts, xdouts
         torch.cuda.synchronize()
 
+    # ---- measured device ceilings: plain device copy and FP64 FMA chains ----
+    ceilings = None
+    if not args.no_ceilings and args.copy_check == 0:   # a byte-counter calibration run keeps one copy only
+        log("ceilings")
+        cb = 1 << 31
+        csrc = torch.ones(cb // 8, dtype=torch.float64, device=dev)
+        cdst = torch.empty_like(csrc)
+        ms_c, _ = timed(eng, lambda: cdst.copy_(csrc), 5, 1)
+        del csrc, cdst
+        cout = torch.empty(4096 * 256, dtype=torch.float64, device=dev)
+        fl = [0.0]
+
+        def fma_run():
+            fl[0] = eng.fp64_ceiling(20000, 4096, cout)
+
+        ms_f, _ = timed(eng, fma_run, 3, 1)
+        assert bool(torch.isfinite(cout).all().item())
+        del cout
+        ceilings = {"copy_gbs": round(2 * cb / (ms_c / 1e3) / 1e9, 1),
+                    "copy": "torch copy_ of 2 GiB f64 (read + write counted), HIP events",
+                    "fp64_tflops": round(fl[0] / (ms_f / 1e3) / 1e12, 2),
+                    "fp64": "shg_fp64_ceiling: 4096 x 256 threads x 20000 rounds x 8 independent FMA chains"}
+        torch.cuda.synchronize()
+
     # ---- roofline of the dominant kernel of the value path ----
     per = []
     skip_mask = {}
@@ -324,6 +349,10 @@ def main():
     roofline["launches_averaged"] = {"ops": gops, "per_op_ms": {op: round(k, 4) for _, k, _, _, op in per}}
     roofline["step_share"] = round(kms_sum / ms_s, 3)
     roofline["traffic"] = stored_traffic(name)
+    if ceilings:
+        roofline["measured_ceilings"] = ceilings
+        roofline["frac_of_measured_copy"] = round(roofline["achieved"] / ceilings["copy_gbs"], 4)
+        roofline["fp64_frac_of_measured"] = round(roofline["fp64_tflops"] / ceilings["fp64_tflops"], 4)
 
     for p in splans:
         p.close()

@@ -123,6 +123,14 @@ int shg_pairs_swap(shg_ctx *ctx, const shg_shells *sh, const int32_t *pairs, int
                    const int64_t *src_off, const int64_t *dst_off, double *out, double *dout);
 int shg_pairs_swap_check(shg_ctx *ctx);
 
+/* Measurement utility, not part of the method: launches `blocks` workgroups
+ * of 256 threads, each thread running `iters` rounds of 8 independent FP64
+ * FMA chains with no memory traffic, on the context's stream; out (device,
+ * >= blocks*256 doubles) receives one result per thread; *flops (host)
+ * receives the floating-point operations of the launch (2 per FMA). The
+ * caller times the launch; the ratio is the FP64 rate the device sustains. */
+int shg_fp64_ceiling(shg_ctx *ctx, int64_t iters, int blocks, double *out, double *flops);
+
 /* Three-index overlap (a b a~) (Sec. II.D, eq. aba_integrals): a = orb shell
  * t[0] and a~ = aux shell t[1] share center A (their centers must be equal
  * bit for bit, else SHG_EINVAL), b = orb shell t[2].

@@ -68,6 +68,8 @@ def load_library(path: str = LIB_PATH):
     lib.shg_pairs_swap.restype = C.c_int
     lib.shg_pairs_swap_check.argtypes = [P]
     lib.shg_pairs_swap_check.restype = C.c_int
+    lib.shg_fp64_ceiling.argtypes = [P, C.c_int64, C.c_int, P, C.POINTER(C.c_double)]
+    lib.shg_fp64_ceiling.restype = C.c_int
     I = C.c_int
     lib.shg_set_tile_shape.argtypes = [P, I, I, I, I, I, I]
     lib.shg_get_tile_shape.argtypes = [P, I, I, I, I, C.POINTER(I), C.POINTER(I)]
@@ -223,6 +225,12 @@ class Engine:
                                             _ptr(out), _ptr(dout)))
         if check:
             self._check(self.lib.shg_pairs_swap_check(self.ctx))
+
+    def fp64_ceiling(self, iters: int, blocks: int, out) -> float:
+        """shg_fp64_ceiling: launch the FMA-chain kernel; returns its flop count."""
+        fl = C.c_double()
+        self._check(self.lib.shg_fp64_ceiling(self.ctx, int(iters), int(blocks), _ptr(out), C.byref(fl)))
+        return fl.value
 
     def aab(self, orb: DeviceShells, aux: DeviceShells, triples, out_off, out, dout=None):
         n = int(triples.shape[0])
