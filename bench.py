@@ -521,6 +521,13 @@ def main():
                    "blocks_per_step": blocks_per_step},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "paper_context": {
+            "what": "the paper's OS/SHG speed-up ratios (Table 3, MOLOPT basis sets, integrals + derivatives), "
+                    "measured in CP2K on one Xeon E5-2697v3 (Haswell); context only, other hardware and code",
+            "os_over_shg_int_dev_range": {"overlap": [2.4, 10.3], "coulomb": [6.2, 31.6], "erf": [6.0, 31.7],
+                                          "erfc": [5.4, 29.5], "gauss": [6.7, 32.5], "aab": [7.2, 10.5],
+                                          "gcoulomb": [5.0, 25.4], "r2n_n1": [2.7, 18.6], "r2n_n5": [10.5, 79.9]},
+            "gpu_shg_over_cpu_oracle": (round(value / cpu["value"], 1) if cpu and cpu.get("value") else None)},
         "paths": res_paths,
         "speedup_vs_plain": round(ms_plain / ms_s, 3),
         "screening": screening,
