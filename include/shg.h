@@ -54,8 +54,9 @@ typedef enum {
     SHG_ERFC    = 3,   /* erfc(omega r)/r  (short range)  omega > 0    */
     SHG_GAUSS   = 4,   /* exp(-omega r^2)                 omega > 0    */
     SHG_GCOULOMB = 5   /* exp(-omega r^2)/r               omega > 0;
-                          shg_pairs / shg_pairs_deriv only (not in plans,
-                          screening or tuning calls) */
+                          shg_pairs, shg_pairs_deriv and shg_plan_create
+                          (not in screened or multi-operator plans, nor in
+                          shg_autotune) */
 } shg_op;
 
 /* Shell table. All arrays are DEVICE arrays of length nshell (prim arrays of

@@ -115,7 +115,13 @@ __global__ void k_classify(int64_t n, const int32_t *pairs, int nshell, const in
 __global__ void k_scan_bins(const int32_t *hist, int nb, int32_t *starts, int32_t *cursor);
 __global__ void k_scatter(int64_t n, const int32_t *keys, int32_t *cursor, int32_t *order, const int32_t *pairs,
                           const int64_t *out_off, PairRec *rec);
-// exp(-omega r^2)/r pairs through the precomputed-monopole tiles (shg_monopole.hip)
+// exp(-omega r^2)/r pairs through the precomputed-monopole tiles (shg_monopole.hip);
+// gc_radial_range writes the radial terms of sorted positions [start, start +
+// count) of one class to T[pos * MONO_TSTRIDE + k]
+constexpr int MONO_TSTRIDE = 8;
+void gc_radial_range(hipStream_t s, int cls, bool deriv, const shg_shells *sh, const int32_t *pairs,
+                     const int32_t *order, const double *w, const double *tab, double omega, double *T, int64_t start,
+                     int64_t count);
 int gcoulomb_pairs(shg_ctx *c, const char *what, double omega, const shg_shells *sh, const int32_t *pairs, int64_t n,
                    const int64_t *out_off, double *out, double *dout);
 // screening decisions (shg_screen.hip): keep[i] = 0 if pair i may be skipped

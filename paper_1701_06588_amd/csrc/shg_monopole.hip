@@ -36,7 +36,7 @@ using namespace shg;
 namespace {
 
 constexpr int R2N_MAX = 5;
-constexpr int R2N_TSTRIDE = 8;            // doubles per pair in the radial-term buffer (NK <= 6)
+constexpr int R2N_TSTRIDE = MONO_TSTRIDE;  // doubles per pair in the radial-term buffer (NK <= 6)
 constexpr int64_t MONO_CHUNK = 1 << 20;
 constexpr int RG = 8, RTPB = 256;         // lanes per pair, threads per block
 
@@ -280,6 +280,15 @@ int monopole_pairs(shg_ctx *c, const char *what, const rad_fn *rtab, int nr, dou
 }  // namespace
 
 namespace shg {
+void gc_radial_range(hipStream_t s, int cls, bool deriv, const shg_shells *sh, const int32_t *pairs,
+                     const int32_t *order, const double *w, const double *tab, double omega, double *T, int64_t start,
+                     int64_t count)
+{
+    R2nArgs ra{pairs, order, sh->center, sh->nprim, sh->prim_off, sh->exps, w, T + start * R2N_TSTRIDE,
+               start, count, 0, omega, tab};
+    gc_table()[cls * 2 + (deriv ? 1 : 0)](s, ra);
+}
+
 int gcoulomb_pairs(shg_ctx *c, const char *what, double omega, const shg_shells *sh, const int32_t *pairs, int64_t n,
                    const int64_t *out_off, double *out, double *dout)
 {

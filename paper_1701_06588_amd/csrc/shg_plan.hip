@@ -48,7 +48,40 @@ struct shg_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<int32_t> skipped;     // pair ids removed by screening
+    double *T = nullptr;              // exp(-omega r^2)/r: radial terms per sorted position
 };
+
+__global__ void k_make_recs(int64_t n, const int32_t *order, const int32_t *pairs, const int64_t *out_off, PairRec *rec);
+
+// tile arguments of a plan: two-center mode, or for exp(-omega r^2)/r the
+// precomputed-monopole mode over the plan's radial-term buffer
+static TileArgs plan_tile_args(const shg_plan *p)
+{
+    TileArgs ta{p->rec, p->order, p->sh.center, p->sh.nprim, p->sh.prim_off, p->sh.exps, p->w, p->ctx->boys, p->out,
+                p->dout, p->omega, p->op};
+    if (p->op == SHG_GCOULOMB) {
+        ta.triples = p->pairs;
+        ta.tstride = 2;
+        ta.ooff = p->out_off;
+        ta.P = p->T;
+        ta.pstride = MONO_TSTRIDE;
+        ta.poff = 0;
+        ta.ybase = 0;
+    }
+    return ta;
+}
+
+// the radial stage of the operators evaluated in precomputed-monopole mode
+static void plan_radial(const shg_plan *p, hipStream_t s)
+{
+    if (p->op != SHG_GCOULOMB) return;
+    for (int cls = 0; cls < NCLASS; ++cls) {
+        const int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
+        if (b1 > b0)
+            gc_radial_range(s, cls, p->deriv != 0, &p->sh, p->pairs, p->order, p->w, p->ctx->boys, p->omega, p->T,
+                            b0, b1 - b0);
+    }
+}
 
 static int plan_enqueue(shg_plan *p, hipStream_t s)
 {
@@ -57,8 +90,8 @@ static int plan_enqueue(shg_plan *p, hipStream_t s)
     if (sh->nshell > 0)
         hipLaunchKernelGGL(k_prep_shells, dim3((sh->nshell + 3) / 4), dim3(256), 0, s, sh->nshell, sh->l, sh->nprim,
                            sh->prim_off, sh->exps, sh->coefs, sh->nprim_total, LMAX, p->w, c->err);
-    TileArgs ta{p->rec, p->order, sh->center, sh->nprim, sh->prim_off, sh->exps, p->w, c->boys, p->out, p->dout,
-                p->omega, p->op};
+    plan_radial(p, s);
+    const TileArgs ta = plan_tile_args(p);
     if (p->nops > 0) {
         if (p->ntiles > 0) {
             hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
@@ -197,8 +230,7 @@ extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, doub
 {
     if (!c || !plan) return SHG_EINVAL;
     *plan = nullptr;
-    if ((int)op < 0 || (int)op > 4)
-        return set_err(c, SHG_EINVAL, "shg_plan_create: operator %d is not available in plans", (int)op);
+    if ((int)op < 0 || (int)op > 5) return set_err(c, SHG_EINVAL, "shg_plan_create: unknown operator %d", (int)op);
     const bool deriv = dout != nullptr;
     // evaluate once through the plain path: validates the input and bins the pairs
     int rc = deriv ? shg_pairs_deriv(c, sh, op, omega, pairs, n, out_off, out, dout)
@@ -218,17 +250,26 @@ extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, doub
     p->deriv = deriv ? 1 : 0;
     p->mode = (flags & SHG_PLAN_PERSISTENT) ? 1 : 0;
     for (int cls = 0; cls <= NCLASS; ++cls) p->cls_start[cls] = n > 0 ? c->host_rb[cls * 64] : 0;
-    for (int cls = 0; cls < NCLASS; ++cls) p->shapes[cls] = c->shape[op][cls / (LMAX + 1)][cls % (LMAX + 1)][p->deriv];
+    const int sop = op == SHG_GCOULOMB ? (int)SHG_COULOMB : (int)op;   // tuned shapes of the nearest operator
+    for (int cls = 0; cls < NCLASS; ++cls) p->shapes[cls] = c->shape[sop][cls / (LMAX + 1)][cls % (LMAX + 1)][p->deriv];
     auto fail = [&](int code) { shg_plan_destroy(p); return code; };
     hipError_t e = hipMalloc((void **)&p->order, std::max<int64_t>(n, 1) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void **)&p->rec, std::max<int64_t>(n, 1) * sizeof(PairRec));
     if (e == hipSuccess) e = hipMalloc((void **)&p->w, std::max<int64_t>(sh->nprim_total, 1) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&p->counter, 64 * sizeof(int));
+    if (e == hipSuccess && op == SHG_GCOULOMB)
+        e = hipMalloc((void **)&p->T, std::max<int64_t>(n, 1) * MONO_TSTRIDE * sizeof(double));
     if (e != hipSuccess) return fail(set_err(c, SHG_ENOMEM, "shg_plan_create: %s", hipGetErrorString(e)));
     if (n > 0) {
         e = hipMemcpyAsync(p->order, c->order, n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream);
-        if (e == hipSuccess)
+        if (e == hipSuccess && op == SHG_GCOULOMB) {
+            // the precomputed-monopole path leaves no pair records in the context
+            hipLaunchKernelGGL(k_make_recs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, p->order,
+                               pairs, out_off, p->rec);
+            e = hipGetLastError();
+        } else if (e == hipSuccess) {
             e = hipMemcpyAsync(p->rec, c->rec, n * sizeof(PairRec), hipMemcpyDeviceToDevice, c->stream);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return fail(set_err(c, SHG_EDEVICE, "shg_plan_create: %s", hipGetErrorString(e)));
     }
@@ -548,12 +589,12 @@ extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
-    TileArgs ta{p->rec, p->order, p->sh.center, p->sh.nprim, p->sh.prim_off, p->sh.exps, p->w, c->boys, p->out,
-                p->dout, p->omega, p->op};
+    const TileArgs ta = plan_tile_args(p);
     double tot = 0;
     for (int r = 0; r < reps; ++r) {
         if (p->mode >= 1) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, 1);
         HIP_TRY(c, hipEventRecord(e0, c->stream));
+        plan_radial(p, c->stream);
         if (p->nops > 0) {
             multi_fn f;
             multi_occ_fn occ;
@@ -594,6 +635,7 @@ extern "C" void shg_plan_destroy(shg_plan *p)
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     (void)hipFree(p->order);
     (void)hipFree(p->rec);
+    (void)hipFree(p->T);
     (void)hipFree(p->w);
     (void)hipFree(p->queue);
     (void)hipFree(p->counter);

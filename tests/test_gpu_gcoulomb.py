@@ -70,8 +70,8 @@ def test_gcoulomb_errors_and_plans(engine):
     for bad in (0.0, -1.0, float("inf")):
         with pytest.raises(shg.ShgError):
             engine.pairs(dsh, "gcoulomb", bad, p, oo, out)
-    with pytest.raises(shg.ShgError):
-        shg.Plan(engine, dsh, "gcoulomb", OMEGA, p, oo, out)
+    with pytest.raises(shg.ShgError):   # screening has no bound for this operator
+        shg.Plan(engine, dsh, "gcoulomb", OMEGA, p, oo, out, tau=1e-12)
     # the context stays usable
     a = run_gc(engine, w, False)
     b = run_gc(engine, w, False)
@@ -94,3 +94,36 @@ def test_gcoulomb_full_five_ops500_sampled(engine):
     gotd = np.concatenate([dout[3 * off[i]:3 * off[i] + 3 * sz[i]] for i in idx])
     assert_parity(got, ro, sub_off, sz[idx], False, "gcoulomb five_ops500")
     assert_parity(gotd, rd, sub_off, sz[idx], True, "gcoulomb five_ops500 d/dR_a")
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_gcoulomb_plan_matches_plain(engine, flags):
+    """Plans (radial stage and precomputed-monopole tiles in one graph; per-class
+    launches or the persistent kernel) against the plain path, replayed twice
+    with the library's own work in between, then autotuned."""
+    import torch
+    from paper_1701_06588_amd import shg
+    w = inputs.small_pairs(2027, 2500)
+    print(f"case gcoulomb plan flags={flags}", flush=True)
+    off, sz, ref, dref = run_gc(engine, w, True)
+    dev = torch.device("cuda")
+    dsh = engine.shells(w.shells)
+    p = torch.as_tensor(np.ascontiguousarray(w.pairs, np.int32), device=dev)
+    oo = torch.as_tensor(off, device=dev)
+    out = torch.full((len(ref),), float("nan"), dtype=torch.float64, device=dev)
+    dout = torch.full((len(dref),), float("nan"), dtype=torch.float64, device=dev)
+    plan = shg.Plan(engine, dsh, "gcoulomb", OMEGA, p, oo, out, dout, flags=flags)
+    for rep in range(2):
+        out.fill_(float("nan"))
+        dout.fill_(float("nan"))
+        plan.execute()
+        torch.cuda.synchronize()
+        assert_parity(out.cpu().numpy(), ref, off, sz, False, f"plan rep {rep}")
+        assert_parity(dout.cpu().numpy(), dref, off, sz, True, f"plan rep {rep} d/dR_a")
+        run_gc(engine, w, False)     # other work on the library between replays
+    plan.autotune(2)
+    out.fill_(float("nan"))
+    plan.execute()
+    torch.cuda.synchronize()
+    assert_parity(out.cpu().numpy(), ref, off, sz, False, f"plan autotuned ({plan.mode})")
+    plan.close()
