@@ -448,6 +448,12 @@ def main():
                            steps5, 1)
             r2n[f"n{nr}"] = {"ms_per_call": round(ms5, 4), "blocks_per_s": round(n / (ms5 / 1e3), 1),
                              "hbm_frac": round(b_r2n / (ms5 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        rplan = shg.Plan(eng, dsh, "r2n", 0.0, pairs, out_off, outs[ops[0]], douts[ops[0]], nr=3)
+        rplan.autotune(2)
+        ms8, _ = timed(eng, rplan.execute, steps5, 1)
+        r2n["n3_batched"] = {"ms_per_call": round(ms8, 4), "blocks_per_s": round(n / (ms8 / 1e3), 1),
+                             "mode": rplan.mode}
+        rplan.close()
         extra["r2n"] = r2n
         ms6, _ = timed(eng, lambda: eng.pairs(dsh, "gcoulomb", 0.7, pairs, out_off, outs[ops[0]], douts[ops[0]]),
                        steps5, 1)

@@ -234,6 +234,13 @@ int  shg_screen_features(shg_ctx *ctx, const shg_shells *sh, shg_op op, double o
 /* log10 max|block| (clamped at -30) of evaluated blocks (training targets) */
 int  shg_block_logmax(shg_ctx *ctx, const shg_shells *sh, const int32_t *pairs, int64_t n,
                       const int64_t *out_off, const double *out, float *y);
+
+/* A plan for (a|r_a^{2n}|b) (Sec. II.C, as shg_pairs_r2n, 0 <= nr <= 5):
+ * arguments, flags, validation and ownership as in shg_plan_create; the
+ * recorded evaluation runs the monopole stage and then the tiles. */
+int shg_plan_create_r2n(shg_ctx *ctx, const shg_shells *sh, int nr, const int32_t *pairs, int64_t n,
+                        const int64_t *out_off, double *out, double *dout, unsigned flags, shg_plan **plan);
+
 /* Screened plan: as shg_plan_create, then every pair whose analytic bound is
  * below tau, or (mlp non-NULL, features in range) whose prediction plus the
  * model margin is below log10(tau), is skipped: its block is set to zero once

@@ -122,6 +122,9 @@ constexpr int MONO_TSTRIDE = 8;
 void gc_radial_range(hipStream_t s, int cls, bool deriv, const shg_shells *sh, const int32_t *pairs,
                      const int32_t *order, const double *w, const double *tab, double omega, double *T, int64_t start,
                      int64_t count);
+// the same for (a|r_a^{2n}|b), 0 <= nr <= 5
+void r2n_radial_range(hipStream_t s, int cls, bool deriv, const shg_shells *sh, const int32_t *pairs,
+                      const int32_t *order, const double *w, int nr, double *T, int64_t start, int64_t count);
 int gcoulomb_pairs(shg_ctx *c, const char *what, double omega, const shg_shells *sh, const int32_t *pairs, int64_t n,
                    const int64_t *out_off, double *out, double *dout);
 // screening decisions (shg_screen.hip): keep[i] = 0 if pair i may be skipped

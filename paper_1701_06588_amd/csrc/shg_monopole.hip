@@ -289,6 +289,14 @@ void gc_radial_range(hipStream_t s, int cls, bool deriv, const shg_shells *sh, c
     gc_table()[cls * 2 + (deriv ? 1 : 0)](s, ra);
 }
 
+void r2n_radial_range(hipStream_t s, int cls, bool deriv, const shg_shells *sh, const int32_t *pairs,
+                      const int32_t *order, const double *w, int nr, double *T, int64_t start, int64_t count)
+{
+    R2nArgs ra{pairs, order, sh->center, sh->nprim, sh->prim_off, sh->exps, w, T + start * R2N_TSTRIDE,
+               start, count, nr, 0.0, nullptr};
+    r2n_table()[cls * 2 + (deriv ? 1 : 0)](s, ra);
+}
+
 int gcoulomb_pairs(shg_ctx *c, const char *what, double omega, const shg_shells *sh, const int32_t *pairs, int64_t n,
                    const int64_t *out_off, double *out, double *dout)
 {

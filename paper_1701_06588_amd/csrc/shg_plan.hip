@@ -48,8 +48,13 @@ struct shg_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<int32_t> skipped;     // pair ids removed by screening
-    double *T = nullptr;              // exp(-omega r^2)/r: radial terms per sorted position
+    double *T = nullptr;              // precomputed-monopole operators: radial terms per sorted position
+    int nr = 0;                       // (a|r_a^{2n}|b): n
 };
+
+// plan operator code of (a|r_a^{2n}|b) (outside the shg_op range)
+constexpr int PLAN_OP_R2N = 16;
+static bool plan_mono(int op) { return op == SHG_GCOULOMB || op == PLAN_OP_R2N; }
 
 __global__ void k_make_recs(int64_t n, const int32_t *order, const int32_t *pairs, const int64_t *out_off, PairRec *rec);
 
@@ -59,7 +64,7 @@ static TileArgs plan_tile_args(const shg_plan *p)
 {
     TileArgs ta{p->rec, p->order, p->sh.center, p->sh.nprim, p->sh.prim_off, p->sh.exps, p->w, p->ctx->boys, p->out,
                 p->dout, p->omega, p->op};
-    if (p->op == SHG_GCOULOMB) {
+    if (plan_mono(p->op)) {
         ta.triples = p->pairs;
         ta.tstride = 2;
         ta.ooff = p->out_off;
@@ -74,12 +79,15 @@ static TileArgs plan_tile_args(const shg_plan *p)
 // the radial stage of the operators evaluated in precomputed-monopole mode
 static void plan_radial(const shg_plan *p, hipStream_t s)
 {
-    if (p->op != SHG_GCOULOMB) return;
+    if (!plan_mono(p->op)) return;
     for (int cls = 0; cls < NCLASS; ++cls) {
         const int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
-        if (b1 > b0)
+        if (b1 <= b0) continue;
+        if (p->op == SHG_GCOULOMB)
             gc_radial_range(s, cls, p->deriv != 0, &p->sh, p->pairs, p->order, p->w, p->ctx->boys, p->omega, p->T,
                             b0, b1 - b0);
+        else
+            r2n_radial_range(s, cls, p->deriv != 0, &p->sh, p->pairs, p->order, p->w, p->nr, p->T, b0, b1 - b0);
     }
 }
 
@@ -224,23 +232,22 @@ static int plan_build_queue(shg_plan *p)
     return 0;
 }
 
-extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
-                               int64_t n, const int64_t *out_off, double *out, double *dout, unsigned flags,
-                               shg_plan **plan)
+static int plan_create_impl(shg_ctx *c, const shg_shells *sh, int op, double omega, int nr, const int32_t *pairs,
+                            int64_t n, const int64_t *out_off, double *out, double *dout, unsigned flags,
+                            shg_plan **plan)
 {
-    if (!c || !plan) return SHG_EINVAL;
-    *plan = nullptr;
-    if ((int)op < 0 || (int)op > 5) return set_err(c, SHG_EINVAL, "shg_plan_create: unknown operator %d", (int)op);
     const bool deriv = dout != nullptr;
     // evaluate once through the plain path: validates the input and bins the pairs
-    int rc = deriv ? shg_pairs_deriv(c, sh, op, omega, pairs, n, out_off, out, dout)
-                   : shg_pairs(c, sh, op, omega, pairs, n, out_off, out);
+    int rc = op == PLAN_OP_R2N ? shg_pairs_r2n(c, sh, nr, pairs, n, out_off, out, dout)
+             : deriv           ? shg_pairs_deriv(c, sh, (shg_op)op, omega, pairs, n, out_off, out, dout)
+                               : shg_pairs(c, sh, (shg_op)op, omega, pairs, n, out_off, out);
     if (rc) return rc;
     shg_plan *p = new (std::nothrow) shg_plan();
     if (!p) return set_err(c, SHG_ENOMEM, "shg_plan_create: out of host memory");
     p->ctx = c;
     p->sh = *sh;
-    p->op = (int)op;
+    p->op = op;
+    p->nr = nr;
     p->omega = omega;
     p->pairs = pairs;
     p->n = n;
@@ -250,19 +257,20 @@ extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, doub
     p->deriv = deriv ? 1 : 0;
     p->mode = (flags & SHG_PLAN_PERSISTENT) ? 1 : 0;
     for (int cls = 0; cls <= NCLASS; ++cls) p->cls_start[cls] = n > 0 ? c->host_rb[cls * 64] : 0;
-    const int sop = op == SHG_GCOULOMB ? (int)SHG_COULOMB : (int)op;   // tuned shapes of the nearest operator
+    // tuned shapes of the nearest in-kernel operator
+    const int sop = op == SHG_GCOULOMB ? (int)SHG_COULOMB : op == PLAN_OP_R2N ? (int)SHG_OVERLAP : op;
     for (int cls = 0; cls < NCLASS; ++cls) p->shapes[cls] = c->shape[sop][cls / (LMAX + 1)][cls % (LMAX + 1)][p->deriv];
     auto fail = [&](int code) { shg_plan_destroy(p); return code; };
     hipError_t e = hipMalloc((void **)&p->order, std::max<int64_t>(n, 1) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void **)&p->rec, std::max<int64_t>(n, 1) * sizeof(PairRec));
     if (e == hipSuccess) e = hipMalloc((void **)&p->w, std::max<int64_t>(sh->nprim_total, 1) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&p->counter, 64 * sizeof(int));
-    if (e == hipSuccess && op == SHG_GCOULOMB)
+    if (e == hipSuccess && plan_mono(op))
         e = hipMalloc((void **)&p->T, std::max<int64_t>(n, 1) * MONO_TSTRIDE * sizeof(double));
     if (e != hipSuccess) return fail(set_err(c, SHG_ENOMEM, "shg_plan_create: %s", hipGetErrorString(e)));
     if (n > 0) {
         e = hipMemcpyAsync(p->order, c->order, n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream);
-        if (e == hipSuccess && op == SHG_GCOULOMB) {
+        if (e == hipSuccess && plan_mono(op)) {
             // the precomputed-monopole path leaves no pair records in the context
             hipLaunchKernelGGL(k_make_recs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, p->order,
                                pairs, out_off, p->rec);
@@ -277,6 +285,24 @@ extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, doub
     if (!(flags & SHG_PLAN_NO_GRAPH) && (rc = plan_capture(p))) return fail(rc);
     *plan = p;
     return 0;
+}
+
+extern "C" int shg_plan_create(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
+                               int64_t n, const int64_t *out_off, double *out, double *dout, unsigned flags,
+                               shg_plan **plan)
+{
+    if (!c || !plan) return SHG_EINVAL;
+    *plan = nullptr;
+    if ((int)op < 0 || (int)op > 5) return set_err(c, SHG_EINVAL, "shg_plan_create: unknown operator %d", (int)op);
+    return plan_create_impl(c, sh, (int)op, omega, 0, pairs, n, out_off, out, dout, flags, plan);
+}
+
+extern "C" int shg_plan_create_r2n(shg_ctx *c, const shg_shells *sh, int nr, const int32_t *pairs, int64_t n,
+                                   const int64_t *out_off, double *out, double *dout, unsigned flags, shg_plan **plan)
+{
+    if (!c || !plan) return SHG_EINVAL;
+    *plan = nullptr;
+    return plan_create_impl(c, sh, PLAN_OP_R2N, 0.0, nr, pairs, n, out_off, out, dout, flags, plan);
 }
 
 // records of the pairs in `order` (after screening removed some)

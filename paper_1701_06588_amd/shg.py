@@ -81,6 +81,9 @@ def load_library(path: str = LIB_PATH):
                                      C.POINTER(C.c_int64)]
     lib.shg_plan_create.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, P, P, P, C.c_uint,
                                     C.POINTER(C.c_void_p)]
+    lib.shg_plan_create_r2n.argtypes = [P, C.POINTER(ShgShells), I, P, C.c_int64, P, P, P, C.c_uint,
+                                        C.POINTER(C.c_void_p)]
+    lib.shg_plan_create_r2n.restype = C.c_int
     lib.shg_plan_execute.argtypes = [P]
     lib.shg_plan_autotune.argtypes = [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.shg_plan_set_mode.argtypes = [P, I]
@@ -249,12 +252,17 @@ class Plan:
     bound, or (with `mlp`) learned prediction plus margin, is below tau are skipped."""
 
     def __init__(self, engine: "Engine", dsh: DeviceShells, op: str, omega: float, pairs, out_off, out, dout=None,
-                 flags: int = 0, tau: float | None = None, mlp: "Mlp | None" = None):
+                 flags: int = 0, tau: float | None = None, mlp: "Mlp | None" = None, nr: int | None = None):
+        """op "r2n" with `nr` records (a|r_a^{2n}|b) (shg_plan_create_r2n; omega ignored)."""
         self.engine = engine
         self.keep = (dsh, pairs, out_off, out, dout, mlp)   # the plan references these buffers
         h = C.c_void_p()
         self.n_skipped = 0
-        if tau is None:
+        if op == "r2n":
+            engine._check(engine.lib.shg_plan_create_r2n(engine.ctx, C.byref(dsh.c), int(nr), _ptr(pairs),
+                                                         int(pairs.shape[0]), _ptr(out_off), _ptr(out), _ptr(dout),
+                                                         int(flags), C.byref(h)))
+        elif tau is None:
             engine._check(engine.lib.shg_plan_create(engine.ctx, C.byref(dsh.c), OPS[op], float(omega),
                                                      _ptr(pairs), int(pairs.shape[0]), _ptr(out_off), _ptr(out),
                                                      _ptr(dout), int(flags), C.byref(h)))

@@ -122,3 +122,38 @@ def test_r2n_full_five_ops500_sampled(engine):
     gotd = np.concatenate([dout[3 * off[i]:3 * off[i] + 3 * sz[i]] for i in idx])
     assert_parity(got, ro, sub_off, sz[idx], False, "r2n five_ops500")
     assert_parity(gotd, rd, sub_off, sz[idx], True, "r2n five_ops500 d/dR_a")
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_r2n_plan_matches_plain(engine, flags):
+    """shg_plan_create_r2n (monopole stage and precomputed-monopole tiles in one
+    graph; per-class launches or the persistent kernel) against the plain path,
+    replayed twice with other library work in between, then autotuned."""
+    import torch
+    from paper_1701_06588_amd import shg
+    w = small()
+    print(f"case r2n plan n=4 flags={flags}", flush=True)
+    off, sz, ref, dref = run_r2n(engine, w, 4, True)
+    dev = torch.device("cuda")
+    dsh = engine.shells(w.shells)
+    p = torch.as_tensor(np.ascontiguousarray(w.pairs, np.int32), device=dev)
+    oo = torch.as_tensor(off, device=dev)
+    out = torch.full((len(ref),), float("nan"), dtype=torch.float64, device=dev)
+    dout = torch.full((len(dref),), float("nan"), dtype=torch.float64, device=dev)
+    plan = shg.Plan(engine, dsh, "r2n", 0.0, p, oo, out, dout, flags=flags, nr=4)
+    for rep in range(2):
+        out.fill_(float("nan"))
+        dout.fill_(float("nan"))
+        plan.execute()
+        torch.cuda.synchronize()
+        assert_parity(out.cpu().numpy(), ref, off, sz, False, f"r2n plan rep {rep}")
+        assert_parity(dout.cpu().numpy(), dref, off, sz, True, f"r2n plan rep {rep} d/dR_a")
+        run_r2n(engine, w, 1, False)
+    plan.autotune(2)
+    out.fill_(float("nan"))
+    plan.execute()
+    torch.cuda.synchronize()
+    assert_parity(out.cpu().numpy(), ref, off, sz, False, f"r2n plan autotuned ({plan.mode})")
+    plan.close()
+    with pytest.raises(shg.ShgError):
+        shg.Plan(engine, dsh, "r2n", 0.0, p, oo, out, dout, nr=6)
