@@ -75,3 +75,43 @@ def test_swap_errors(engine):
         engine.pairs_swap(dsh, bad, z, d, out, check=True)
     empty = torch.zeros((0, 2), dtype=torch.int32, device=dev)
     engine.pairs_swap(dsh, empty, z[:0], d[:0], out, check=True)
+
+
+def test_swap_full_five_ops500(engine):
+    """The benchmark's swap configuration at full size (1.61e6 ordered pairs,
+    Coulomb, values + d/dR_a): plan over the pairs with a <= b, the mirror
+    blocks by shg_pairs_swap, every element against the plain evaluation of all
+    pairs (1e-12 relative, 1e-14 of the largest element as floor)."""
+    import torch
+    from paper_1701_06588_amd import shg
+    w = inputs.five_ops500()
+    print(f"case swap five_ops500 pairs={len(w.pairs)}", flush=True)
+    dev = torch.device("cuda")
+    dsh = engine.shells(w.shells)
+    off, tot = w.out_offsets()
+    n = len(w.pairs)
+    a_, b_ = w.pairs[:, 0].astype(np.int64), w.pairs[:, 1].astype(np.int64)
+    key = a_ * int(w.shells.n) + b_
+    kord = np.argsort(key)
+    mir = np.nonzero(a_ > b_)[0]
+    partner = kord[np.searchsorted(key[kord], b_[mir] * int(w.shells.n) + a_[mir])]
+    assert np.all(key[partner] == b_[mir] * int(w.shells.n) + a_[mir])
+    ci = np.nonzero(a_ <= b_)[0]
+    ref = torch.empty(tot, dtype=torch.float64, device=dev)
+    dref = torch.empty(3 * tot, dtype=torch.float64, device=dev)
+    engine.pairs(dsh, "coulomb", 0.0, torch.as_tensor(np.ascontiguousarray(w.pairs, np.int32), device=dev),
+                 torch.as_tensor(off, device=dev), ref, dref)
+    out = torch.full((tot,), float("nan"), dtype=torch.float64, device=dev)
+    dout = torch.full((3 * tot,), float("nan"), dtype=torch.float64, device=dev)
+    plan = shg.Plan(engine, dsh, "coulomb", 0.0, torch.as_tensor(np.ascontiguousarray(w.pairs[ci], np.int32), device=dev),
+                    torch.as_tensor(off[ci], device=dev), out, dout, flags=1)
+    plan.execute()
+    engine.pairs_swap(dsh, torch.as_tensor(np.ascontiguousarray(w.pairs[partner], np.int32), device=dev),
+                      torch.as_tensor(off[partner], device=dev), torch.as_tensor(off[mir], device=dev), out, dout,
+                      check=True)
+    torch.cuda.synchronize()
+    plan.close()
+    for x, r, what in ((out, ref, "values"), (dout, dref, "d/dR_a")):
+        assert bool(torch.isfinite(x).all().item()), what
+        tol = 1e-12 * r.abs() + 1e-14 * max(1.0, r.abs().max().item())
+        assert int(((x - r).abs() > tol).sum().item()) == 0, what
