@@ -55,7 +55,7 @@ typedef enum {
     SHG_GAUSS   = 4,   /* exp(-omega r^2)                 omega > 0    */
     SHG_GCOULOMB = 5   /* exp(-omega r^2)/r               omega > 0;
                           shg_pairs, shg_pairs_deriv and shg_plan_create
-                          (not in screened or multi-operator plans, nor in
+                          (not in screened plans, nor in
                           shg_autotune) */
 } shg_op;
 
@@ -111,6 +111,46 @@ int shg_pairs_deriv(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
 int shg_pairs_r2n(shg_ctx *ctx, const shg_shells *sh, int nr, const int32_t *pairs,
                   int64_t n, const int64_t *out_off, double *out, double *dout);
 
+/* ---- family basis sets (Sec. III) ----------------------------------------
+ * A set is a group of contracted functions on one center that share the set's
+ * K exponents (1 <= K <= SHG_SET_KMAX); each function has its own l
+ * (0..SHG_LMAX_ORB) and K raw contraction coefficients. Within a set the
+ * functions must be grouped by l in non-decreasing order (MOLOPT order:
+ * s, s, p, p, d, ...), 1..SHG_SET_FMAX functions per set. All arrays DEVICE. */
+#define SHG_SET_KMAX 8
+#define SHG_SET_FMAX 16
+typedef struct {
+    int32_t nset;
+    int64_t nexp_total, nfun_total, ncoef_total;
+    const double  *center;    /* [nset][3]                                     */
+    const int32_t *nexp;      /* [nset] K                                      */
+    const int64_t *exp_off;   /* [nset] first exponent of the set in exps      */
+    const double  *exps;      /* [nexp_total] > 0                              */
+    const int32_t *nfun;      /* [nset] contracted functions of the set        */
+    const int64_t *fun_off;   /* [nset] first function in fun_l / coef_off     */
+    const int32_t *fun_l;     /* [nfun_total] l of each function               */
+    const int64_t *coef_off;  /* [nfun_total] first of the function's K raw coefficients in coefs */
+    const double  *coefs;     /* [ncoef_total]                                 */
+} shg_sets;
+
+/* (A|O|B) for n pairs of family sets (Sec. III with eqs. O_rab2_deriv and
+ * final_r12int_ab): per set pair the primitive radial terms are evaluated once
+ * for all its function pairs and contracted as C_a^T G^(k) C_b, and per
+ * (la, lb) the angular factors of each element are formed once for all
+ * function pairs with those l.
+ *   set_pairs [n][2] int32 (set on A, set on B)
+ *   out       block i = nsgf_A x nsgf_B doubles row-major at out[out_off[i]],
+ *             nsgf = sum over the set's functions of 2l+1; rows (and columns)
+ *             in function order, components m = -l..l within a function
+ *   dout      nullable; d/dR_A as x, y, z blocks of nsgf_A x nsgf_B at
+ *             dout[3*out_off[i]]
+ * Each entry equals the (a|O|b) of shg_pairs for the two functions taken as
+ * shells. Operators SHG_OVERLAP..SHG_GAUSS; invalid sets or indices give
+ * SHG_EINVAL. Synchronises the context stream twice (validation, binning). */
+int shg_set_pairs(shg_ctx *ctx, const shg_sets *sets, shg_op op, double omega,
+                  const int32_t *set_pairs, int64_t n, const int64_t *out_off,
+                  double *out, double *dout);
+
 /* Swap symmetry (Sec. V): for the operators of shg_op (even functions of
  * r1 - r2) and each function keeping its center, (b|O|a) = (a|O|b)^T, and by
  * translation invariance d/dR_b (b|O|a) = -(d/dR_a (a|O|b))^T. Given the
@@ -147,6 +187,12 @@ int shg_aab(shg_ctx *ctx, const shg_shells *orb, const shg_shells *aux,
             const int32_t *triples, int64_t n, const int64_t *out_off,
             double *out, double *dout);
 
+/* Work-item size of shg_aab: each (l_a, l_a~, l_b) class is processed in
+ * chunks of at most `chunk` triples (1 <= chunk <= 2^24, default 2^17); the
+ * chunks' scratch (radial terms and two-center blocks) scales with it.
+ * Results do not depend on it. */
+int shg_set_aab_chunk(shg_ctx *ctx, int64_t chunk);
+
 /* ---- batched path ------------------------------------------------------- */
 
 /* A plan fixes one evaluation: shell table, operator, pair list, offsets and
@@ -179,17 +225,32 @@ int  shg_plan_execute(shg_plan *plan);        /* asynchronous on the ctx stream 
  * nullable; -1 when the persistent kernel cannot take the plan's tiles). */
 int  shg_plan_autotune(shg_plan *plan, int reps, double *ms_per_class, double *ms_persistent);
 int  shg_plan_set_mode(shg_plan *plan, int persistent);
-int  shg_plan_mode(const shg_plan *plan);     /* 0 per-class launches, 1 persistent, 2 multi-operator */
+int  shg_plan_mode(const shg_plan *plan);     /* 0 per-class launches, 1 persistent */
 int  shg_plan_tile_order(const shg_plan *plan);  /* 0 heaviest first, 1 alternating ends, 2 round robin */
-/* ids of the pairs a screened plan skips, written to the host array ids
- * (capacity cap, nullable); returns how many there are */
+/* fix the tile order of the persistent queue (0..2; screened plans 0..1)
+ * without timing; re-records the graphs; synchronises the context stream */
+int  shg_plan_set_tile_order(shg_plan *plan, int order);
+/* ids of the pairs the last execution of a screened plan skipped, written to
+ * the host array ids (capacity cap, nullable); returns how many there are (0
+ * for unscreened plans). Synchronises the context stream. */
 int64_t shg_plan_skipped(const shg_plan *plan, int32_t *ids, int64_t cap);
-/* number of pairs a plan evaluates (after screening) and their algorithmic
- * bytes (8 (2la+1)(2lb+1)(1 or 4) per operator + 16 per pair); host pointers */
+/* number of pairs a plan evaluates (a screened plan: at its last execution)
+ * and their algorithmic bytes (8 (2la+1)(2lb+1)(1 or 4) + 16 per pair); host
+ * pointers; synchronises the context stream for screened plans */
 int  shg_plan_stats(const shg_plan *plan, int64_t *kept, int64_t *alg_bytes);
 /* mean duration in ms of the plan's evaluation kernels alone (no shell
  * preparation), timed with HIP events over `reps` runs; synchronous */
 int  shg_plan_kernel_ms(shg_plan *plan, int reps, double *ms);
+/* Kernel timing inside replays: with on != 0, every later shg_plan_execute
+ * records a HIP event pair on the context stream around the plan's evaluation
+ * kernels (the persistent kernel or the per-class launches, recorded as a
+ * graph of their own after the stage graph of shell preparation and, for a
+ * screened plan, the screening stage), for up to 1024 executions.
+ * shg_plan_kernel_time synchronises the context stream, returns (host
+ * pointers) the summed milliseconds and the number of timed executions since
+ * the last call or since timing was switched on, and restarts the count. */
+int  shg_plan_time_kernels(shg_plan *plan, int on);
+int  shg_plan_kernel_time(shg_plan *plan, double *ms_sum, int64_t *executions);
 void shg_plan_destroy(shg_plan *plan);
 
 /* ---- prescreening ------------------------------------------------------ */
@@ -210,6 +271,12 @@ int  shg_mlp_params(shg_mlp *mlp, float *host_out, const float *host_in);
 int  shg_mlp_set_norm(shg_mlp *mlp, const float *mean, const float *std, const float *lo, const float *hi);
 /* calibration margin (log10 units) added to predictions before comparing with tau */
 int  shg_mlp_set_margin(shg_mlp *mlp, float margin);
+/* what the model predicts: ops_mask has bit (1 << op) for every shg_op it was
+ * trained on (SHG_OVERLAP..SHG_GAUSS), deriv_targets != 0 when its targets are
+ * log10 max over the value block and its d/dR_a blocks. Screened plans
+ * consult a model only for an operator in its mask, and for plans with
+ * derivatives only when deriv_targets is set. Saved with the model. */
+int  shg_mlp_set_scope(shg_mlp *mlp, uint32_t ops_mask, int deriv_targets);
 /* one Adam step on a batch: X [B][12] and y [B] device fp32; pinball loss at
  * `quantile` on y - prediction; loss_out (device float, nullable) receives
  * the summed per-sample loss */
@@ -224,16 +291,18 @@ int  shg_mlp_save(shg_mlp *mlp, const char *path);
 int  shg_mlp_load(shg_mlp *mlp, const char *path);
 
 /* The 12 screening features of each pair (device fp32 [n][12]: la, lb,
- * log10 alpha_min/max of a and of b, R, log10(1 + rho_min R^2), log10 bound,
- * erfc flag, omega R, log10(sum|w_a| sum|w_b|)) and log10 of the conservative
- * analytic bound on max|block| (device fp32 [n]); with deriv != 0 the bound
- * covers the d/dR_a elements too (the feature stays the value bound). */
+ * log10 alpha_min/max of a and of b, R, log10(1 + rho_min R^2), log10 of the
+ * bound, operator code (shg_op), omega R for erf/erfc (else 0),
+ * log10(sum|w_a| sum|w_b|)) and log10 of the conservative analytic bound on
+ * max|block| (device fp32 [n]); with deriv != 0 the bound (and the feature)
+ * covers the d/dR_a elements too. */
 int  shg_screen_features(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
                          const int32_t *pairs, int64_t n, int deriv, float *feat,
                          float *log10_bound);
-/* log10 max|block| (clamped at -30) of evaluated blocks (training targets) */
+/* log10 max|element| (clamped at -30) of evaluated blocks (training targets),
+ * over the value block and, with dout non-NULL, its d/dR_a blocks too */
 int  shg_block_logmax(shg_ctx *ctx, const shg_shells *sh, const int32_t *pairs, int64_t n,
-                      const int64_t *out_off, const double *out, float *y);
+                      const int64_t *out_off, const double *out, const double *dout, float *y);
 
 /* A plan for (a|r_a^{2n}|b) (Sec. II.C, as shg_pairs_r2n, 0 <= nr <= 5):
  * arguments, flags, validation and ownership as in shg_plan_create; the
@@ -241,34 +310,25 @@ int  shg_block_logmax(shg_ctx *ctx, const shg_shells *sh, const int32_t *pairs, 
 int shg_plan_create_r2n(shg_ctx *ctx, const shg_shells *sh, int nr, const int32_t *pairs, int64_t n,
                         const int64_t *out_off, double *out, double *dout, unsigned flags, shg_plan **plan);
 
-/* Screened plan: as shg_plan_create, then every pair whose analytic bound is
- * below tau, or (mlp non-NULL, features in range) whose prediction plus the
- * model margin is below log10(tau), is skipped: its block is set to zero once
- * here and never evaluated again; executions evaluate the kept pairs only.
- * With dout the bound covers the d/dR_a elements as well and the model is not
- * consulted (it predicts value magnitudes); it is consulted for SHG_COULOMB
- * and SHG_ERFC only, the operators it is trained on.
- * *n_skipped (host, nullable) receives the number of skipped pairs. */
+/* Screened plan: as shg_plan_create, always recorded, persistent mode. Every
+ * execution decides anew, on the device, which pairs it evaluates, so centers
+ * (or exponents, coefficients) written into the shell buffers between
+ * executions are screened afresh: a pair is skipped when its analytic bound
+ * (values, and with dout the d/dR_a elements too) is below tau, or when a
+ * model (mlp non-NULL, whose scope covers op and, with dout, derivatives;
+ * features inside its training range) predicts, plus its margin, below
+ * log10(tau). Skipped blocks (and their d/dR_a blocks) are set to zero in the
+ * same execution; kept blocks are those of the plain path. The execution
+ * (graph replay) reads nothing back to the host: shell preparation, bound and
+ * model inference, a scan compacting the kept class-sorted pair records, the
+ * tile queue built from the kept counts, the zeroing and the persistent kernel.
+ * The model, if any, must outlive the plan. Operators SHG_OVERLAP..SHG_GAUSS;
+ * tau > 0. Creation executes once; *n_skipped (host, nullable) receives the
+ * number of pairs that execution skipped. */
 int  shg_plan_create_screened(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
                               const int32_t *pairs, int64_t n, const int64_t *out_off,
                               double *out, double *dout, unsigned flags, double tau,
                               shg_mlp *mlp, shg_plan **plan, int64_t *n_skipped);
-
-/* Multi-operator plan: nops (1..5) operators ops[o] with ranges omegas[o] on
- * one pair list, outputs outs[o] (and, douts non-NULL, douts[o]; host arrays
- * of device pointers, kept by the plan). Creation evaluates every operator once
- * through shg_pairs / shg_pairs_deriv; execution evaluates all of them with
- * one persistent kernel that forms each element's angular factors once and
- * applies every operator's contracted radial terms (blocks are bitwise those
- * of the single-operator path). tau > 0 screens with the analytic bound: a
- * pair is skipped (its blocks zeroed once, in every output) only when the
- * bound of every operator is below tau; tau = 0 keeps every pair. Such a plan
- * has one mode (shg_plan_set_mode fails; shg_plan_autotune reports its time
- * as the persistent time and -1 for the per-class time). */
-int  shg_plan_create_multi(shg_ctx *ctx, const shg_shells *sh, int nops, const shg_op *ops,
-                           const double *omegas, const int32_t *pairs, int64_t n,
-                           const int64_t *out_off, double *const *outs, double *const *douts,
-                           double tau, shg_plan **plan, int64_t *n_skipped);
 
 /* ---- tuning and timing ------------------------------------------------- */
 

@@ -61,6 +61,13 @@ def num_threads() -> int:
     return int(_lib().shgo_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """threads of the double-precision build's OpenMP loops (timing only)"""
+    lib = _lib()
+    lib.shgo_set_num_threads.argtypes = [C.c_int]
+    lib.shgo_set_num_threads(int(n))
+
+
 def pairs(shells, op: str, omega: float, pair_idx, out_off=None, deriv=False,
           long_double=False):
     """(a|O|b) blocks (and d/dR_a if ``deriv``) in the flat layout of the C ABI.
@@ -85,6 +92,91 @@ def pairs(shells, op: str, omega: float, pair_idx, out_off=None, deriv=False,
                                       _p(dout) if deriv else None)
     if rc != 0:
         raise ValueError(f"oracle shgo_pairs failed ({rc})")
+    return (out, dout) if deriv else out
+
+
+class _FunctionShells:
+    """every contracted function of a family-set table as a shell of its own
+    (its set's center and exponents, its own l and coefficients)"""
+
+    def __init__(self, sets):
+        centers, ls, ks, exps, coefs = [], [], [], [], []
+        self.first = np.zeros(len(sets.nexp), np.int64)
+        for s in range(len(sets.nexp)):
+            self.first[s] = len(ls)
+            e0, k = int(sets.exp_off[s]), int(sets.nexp[s])
+            for f in range(int(sets.fun_off[s]), int(sets.fun_off[s] + sets.nfun[s])):
+                centers.append(np.asarray(sets.center[s], np.float64))
+                ls.append(int(sets.fun_l[f]))
+                ks.append(k)
+                exps.append(np.asarray(sets.exps[e0:e0 + k], np.float64))
+                coefs.append(np.asarray(sets.coefs[int(sets.coef_off[f]):int(sets.coef_off[f]) + k], np.float64))
+        self.center = np.asarray(centers, np.float64).reshape(-1, 3)
+        self.l = np.asarray(ls, np.int32)
+        self.nprim = np.asarray(ks, np.int32)
+        self.prim_off = np.zeros(len(ks), np.int64)
+        if len(ks):
+            self.prim_off[1:] = np.cumsum(self.nprim[:-1])
+        self.exps = np.concatenate(exps) if exps else np.zeros(0)
+        self.coefs = np.concatenate(coefs) if coefs else np.zeros(0)
+
+    @property
+    def n(self):
+        return int(self.l.shape[0])
+
+
+def set_pairs(sets, op: str, omega: float, set_pair_idx, out_off=None, deriv=False, long_double=False):
+    """Blocks of family-set pairs (Sec. III): for sets A and B with functions
+    f (components m = -l..l, functions in set order) the block is the matrix of
+    every function-pair integral (f_a m_a | O | f_b m_b), nsgf_a x nsgf_b
+    row-major with nsgf = sum over the set's functions of 2l+1, and with
+    ``deriv`` its d/dR_a blocks x, y, z at 3*out_off. By definition each entry
+    is the two-center integral of two contracted functions, so it is computed
+    by ``pairs`` on the functions taken as shells and placed in the block."""
+    fs = _FunctionShells(sets)
+    sp = np.ascontiguousarray(set_pair_idx, np.int64).reshape(-1, 2)
+    nsgf = np.array([int((2 * fs.l[fs.first[s]:fs.first[s] + int(sets.nfun[s])] + 1).sum())
+                     for s in range(len(sets.nexp))], np.int64)
+    sz = nsgf[sp[:, 0]] * nsgf[sp[:, 1]]
+    if out_off is None:
+        out_off = np.zeros(len(sz), np.int64)
+        out_off[1:] = np.cumsum(sz[:-1])
+    total = int((out_off + sz).max()) if len(sz) else 0
+    # every function pair of every set pair, then placed
+    fp, where = [], []
+    for i, (sa, sb) in enumerate(sp):
+        ra = 0
+        for fa in range(int(fs.first[sa]), int(fs.first[sa] + sets.nfun[sa])):
+            na = 2 * int(fs.l[fa]) + 1
+            cb = 0
+            for fb in range(int(fs.first[sb]), int(fs.first[sb] + sets.nfun[sb])):
+                nb = 2 * int(fs.l[fb]) + 1
+                fp.append((fa, fb))
+                where.append((i, ra, cb, na, nb))
+                cb += nb
+            ra += na
+    fp = np.asarray(fp, np.int32).reshape(-1, 2)
+    res = pairs(fs, op, omega, fp, deriv=deriv, long_double=long_double)
+    vals, dvals = (res if deriv else (res, None))
+    fsz = np.array([w[3] * w[4] for w in where], np.int64)
+    foff = np.zeros(len(fsz), np.int64)
+    if len(fsz):
+        foff[1:] = np.cumsum(fsz[:-1])
+    out = np.zeros(total)
+    dout = np.zeros(3 * total) if deriv else None
+    for k, (i, ra, cb, na, nb) in enumerate(where):
+        ld = int(nsgf[sp[i, 1]])
+        blk = int(sz[i])
+        src = vals[foff[k]:foff[k] + na * nb].reshape(na, nb)
+        for r in range(na):
+            o = int(out_off[i]) + (ra + r) * ld + cb
+            out[o:o + nb] = src[r]
+        if deriv:
+            for c in range(3):
+                dsrc = dvals[3 * foff[k] + c * na * nb:3 * foff[k] + (c + 1) * na * nb].reshape(na, nb)
+                for r in range(na):
+                    o = 3 * int(out_off[i]) + c * blk + (ra + r) * ld + cb
+                    dout[o:o + nb] = dsrc[r]
     return (out, dout) if deriv else out
 
 

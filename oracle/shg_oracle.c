@@ -556,6 +556,16 @@ int shgo_num_threads(void)
 #endif
 }
 
+/* threads used by the OpenMP loops of the calls that follow (timing only) */
+void shgo_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int shgo_real_bytes(void) { return (int)sizeof(real); }
 
 void shgo_boys(int nmax, double T, double *F)

@@ -4,7 +4,7 @@
 //   k_prep_shells     weights of the orbital and auxiliary shell tables
 //   k_aab_classify    class key (la, la~, lb) per triple + validation; LDS histogram
 //   k_scan_bins / k_scatter (shared with the two-center path)
-//   per class, in chunks of at most AAB_CHUNK triples, the chunks spread over
+//   per class, in chunks of at most ctx->aab_chunk triples (default 2^17), spread over
 //   AAB_NSTREAM streams (own scratch each; fork/join with events on the
 //   context stream, so the call stays ordered on it):
 //     k_aab_radial    G lanes per triple: P^(k)_{La} for every La of the class from
@@ -30,7 +30,6 @@ namespace {
 constexpr int AAB_LA = 3, AAB_LT = 6, AAB_LB = 3;
 constexpr int AAB_NCLASS = (AAB_LA + 1) * (AAB_LT + 1) * (AAB_LB + 1);
 constexpr int AAB_PSTRIDE = 32;
-constexpr int64_t AAB_CHUNK = 1 << 17;
 constexpr int RAD_G = 8, RAD_TPB = 256;
 
 __device__ __forceinline__ int aab_key(int la, int lt, int lb) { return (la * (AAB_LT + 1) + lt) * (AAB_LB + 1) + lb; }
@@ -345,8 +344,8 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
                 if (ys != (int64_t)NB * (((lamax - lamin) / 2 + 1) * (2 * lamin + 1) +
                                          2 * ((lamax - lamin) / 2 + 1) * ((lamax - lamin) / 2)))
                     return set_err(c, SHG_EDEVICE, "shg_aab: inconsistent Y block layout");
-                for (int64_t c0 = b0; c0 < b1; c0 += AAB_CHUNK) {
-                    const int64_t cn = std::min<int64_t>(AAB_CHUNK, b1 - c0);
+                for (int64_t c0 = b0; c0 < b1; c0 += c->aab_chunk) {
+                    const int64_t cn = std::min<int64_t>(c->aab_chunk, b1 - c0);
                     // Y blocks written and read, output blocks written
                     const double cost = (double)cn * NC * (double)(ys + (2 * la + 1) * (2 * lt + 1) * NB);
                     items.push_back({key, la, lt, lb, lamin, lamax, 0, c0, cn, ys, cost});
@@ -425,5 +424,14 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
     }
     if (first != hipSuccess) return set_err(c, SHG_EDEVICE, "%s: launch failed: %s", what, hipGetErrorString(first));
     HIP_TRY(c, hipGetLastError());
+    return 0;
+}
+
+extern "C" int shg_set_aab_chunk(shg_ctx *c, int64_t chunk)
+{
+    if (!c) return SHG_EINVAL;
+    if (chunk < 1 || chunk > ((int64_t)1 << 24))
+        return set_err(c, SHG_EINVAL, "shg_set_aab_chunk: chunk must be in [1, 2^24]");
+    c->aab_chunk = chunk;
     return 0;
 }

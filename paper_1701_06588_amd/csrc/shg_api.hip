@@ -211,6 +211,11 @@ extern "C" void shg_destroy(shg_ctx *c)
     (void)hipFree(c->rec);
     (void)hipFree(c->bins);
     (void)hipFree(c->stats);
+    (void)hipFree(c->set_w);
+    (void)hipFree(c->set_osz);
+    (void)hipFree(c->set_nsgf);
+    (void)hipFree(c->set_items);
+    (void)hipFree(c->set_O);
     for (int w = 0; w < AAB_NSTREAM; ++w) {
         (void)hipFree(c->Pbuf[w]);
         (void)hipFree(c->Yv[w]);
@@ -258,21 +263,30 @@ int prep_shells(shg_ctx *c, const shg_shells *sh, int lmax, double *&w, size_t &
 int decode_err(shg_ctx *c, int32_t e, const char *what)
 {
     if (!e) return 0;
-    return set_err(c, SHG_EINVAL, "%s: invalid input:%s%s%s%s%s%s", what, (e & ERR_SHELL_L) ? " shell l out of range;" : "",
+    return set_err(c, SHG_EINVAL, "%s: invalid input:%s%s%s%s%s%s%s", what, (e & ERR_SHELL_L) ? " shell l out of range;" : "",
                    (e & ERR_SHELL_K) ? " contraction length outside [1,7] or prim_off out of range;" : "",
                    (e & ERR_SHELL_EXP) ? " exponent not positive and finite;" : "",
                    (e & ERR_PAIR_INDEX) ? " shell index outside [0, nshell);" : "",
                    (e & ERR_AAB_CENTER) ? " a and a~ of a triple are on different centers;" : "",
-                   (e & ERR_AAB_L) ? " l of a triple outside the supported range;" : "");
+                   (e & ERR_AAB_L) ? " l of a triple outside the supported range;" : "",
+                   (e & ERR_SET_FUN) ? " set functions: count outside [1,16], offsets out of range or l not"
+                                       " grouped in non-decreasing order;" : "");
 }
 
 }  // namespace shg
 
-static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
-                        const int64_t *out_off, double *out, double *dout, bool deriv)
+// device scratch of one plain evaluation: folded weights (one per primitive),
+// class keys, class-sorted ids and pair records (one each per pair)
+struct PairScratch {
+    double *w;
+    int32_t *keys, *order;
+    PairRec *rec;
+};
+
+static int pairs_validate(shg_ctx *c, const char *what, const shg_shells *sh, shg_op op, double omega,
+                          const int32_t *pairs, int64_t n, const int64_t *out_off, double *out, double *dout,
+                          bool deriv)
 {
-    const char *what = deriv ? "shg_pairs_deriv" : "shg_pairs";
-    if (!c) return SHG_EINVAL;
     if ((int)op < 0 || (int)op > 4) return set_err(c, SHG_EINVAL, "%s: unknown operator %d", what, (int)op);
     if ((op == SHG_ERF || op == SHG_ERFC || op == SHG_GAUSS) && !(omega > 0.0 && omega < 1e300))
         return set_err(c, SHG_EINVAL, "%s: omega must be positive and finite for this operator", what);
@@ -280,27 +294,33 @@ static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omeg
     if (n >= (int64_t)1 << 31) return set_err(c, SHG_EINVAL, "%s: n >= 2^31 pairs per call", what);
     int rc = check_shells(c, sh, what);
     if (rc) return rc;
-    if (n == 0) return 0;
-    if (!pairs || !out_off || !out || (deriv && !dout)) return set_err(c, SHG_EINVAL, "%s: NULL pointer argument", what);
+    if (n > 0 && (!pairs || !out_off || !out || (deriv && !dout)))
+        return set_err(c, SHG_EINVAL, "%s: NULL pointer argument", what);
+    return 0;
+}
 
-    if ((rc = grow(c, c->keys, c->keys_cap, (size_t)n))) return rc;
-    if ((rc = grow(c, c->order, c->order_cap, (size_t)n))) return rc;
-    if ((rc = grow(c, c->rec, c->rec_cap, (size_t)n))) return rc;
+// binning and per-class launches of one validated call (n > 0) with the given scratch
+static int pairs_run(shg_ctx *c, const char *what, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
+                     int64_t n, const int64_t *out_off, double *out, double *dout, bool deriv, const PairScratch &ps)
+{
+    int rc = 0;
     hipStream_t s = c->stream;
     int32_t *hist = c->bins, *cursor = c->bins + (NBINS_MAX + 1);
     if (c->prof_on) HIP_TRY(c, hipEventRecord(c->ev[0], s));
     hipLaunchKernelGGL(k_fill_i32, dim3((NBINS + 1 + 255) / 256), dim3(256), 0, s, hist, 0, NBINS + 1);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->err, 0, 1);
-    if ((rc = prep_shells(c, sh, LMAX, c->w, c->w_cap))) return rc;
+    if (sh->nshell > 0)
+        hipLaunchKernelGGL(k_prep_shells, dim3((sh->nshell + 3) / 4), dim3(256), 0, s, sh->nshell, sh->l, sh->nprim,
+                           sh->prim_off, sh->exps, sh->coefs, sh->nprim_total, LMAX, ps.w, c->err);
     unsigned gb = (unsigned)((n + BIN_TPB * BIN_ITEMS - 1) / (BIN_TPB * BIN_ITEMS));
-    hipLaunchKernelGGL(k_classify, dim3(gb), dim3(BIN_TPB), 0, s, n, pairs, sh->nshell, sh->l, sh->nprim, c->keys,
+    hipLaunchKernelGGL(k_classify, dim3(gb), dim3(BIN_TPB), 0, s, n, pairs, sh->nshell, sh->l, sh->nprim, ps.keys,
                        hist, c->err);
     // the scan leaves the bin starts in `cursor`; they are read back (class
     // starts are every 64th bin) before the scatter advances the cursors
     hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(256), 0, s, hist, NBINS, cursor, cursor);
     HIP_TRY(c, hipMemcpyAsync(c->host_rb, cursor, (NBINS + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(c->host_rb + NBINS + 1, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(BIN_TPB), 0, s, n, c->keys, cursor, c->order, pairs, out_off, c->rec);
+    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(BIN_TPB), 0, s, n, ps.keys, cursor, ps.order, pairs, out_off, ps.rec);
     if (c->prof_on) HIP_TRY(c, hipEventRecord(c->ev[1], s));
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -309,7 +329,7 @@ static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omeg
     const tile_fn *ttab[5] = {tile_table_la0(), tile_table_la1(), tile_table_la2(), tile_table_la3(),
                               tile_table_la4()};
     const int D = deriv ? 1 : 0;
-    TileArgs ta{c->rec, c->order, sh->center, sh->nprim, sh->prim_off, sh->exps, c->w, c->boys, out, dout,
+    TileArgs ta{ps.rec, ps.order, sh->center, sh->nprim, sh->prim_off, sh->exps, ps.w, c->boys, out, dout,
                 omega, (int)op};
     int prev = NCLASS + 2;   // event before the next class launch
     int used[NCLASS];
@@ -344,6 +364,21 @@ static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omeg
     }
     HIP_TRY(c, hipGetLastError());
     return 0;
+}
+
+static int pairs_common(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
+                        const int64_t *out_off, double *out, double *dout, bool deriv)
+{
+    const char *what = deriv ? "shg_pairs_deriv" : "shg_pairs";
+    if (!c) return SHG_EINVAL;
+    int rc = pairs_validate(c, what, sh, op, omega, pairs, n, out_off, out, dout, deriv);
+    if (rc || n == 0) return rc;
+    if ((rc = grow(c, c->keys, c->keys_cap, (size_t)n))) return rc;
+    if ((rc = grow(c, c->order, c->order_cap, (size_t)n))) return rc;
+    if ((rc = grow(c, c->rec, c->rec_cap, (size_t)n))) return rc;
+    if ((rc = grow(c, c->w, c->w_cap, (size_t)sh->nprim_total + 1))) return rc;
+    return pairs_run(c, what, sh, op, omega, pairs, n, out_off, out, dout, deriv,
+                     PairScratch{c->w, c->keys, c->order, c->rec});
 }
 
 extern "C" int shg_pairs(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,

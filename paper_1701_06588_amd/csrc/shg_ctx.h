@@ -10,10 +10,11 @@
 
 #include "../../include/shg.h"
 #include "shg_kernels.h"
+#include "shg_sets.h"
 
 // error bits raised on the device
 enum { ERR_SHELL_L = 1, ERR_SHELL_K = 2, ERR_SHELL_EXP = 4, ERR_PAIR_INDEX = 8, ERR_AAB_CENTER = 16,
-       ERR_AAB_L = 32 };
+       ERR_AAB_L = 32, ERR_SET_FUN = 64 };
 
 using shg::NCLASS;
 using shg::LMAX;
@@ -51,8 +52,16 @@ struct shg_ctx {
     double *Yv[AAB_NSTREAM] = {}; size_t Yv_cap[AAB_NSTREAM] = {};       // two-center blocks (La|lb) per triple
     double *Yd[AAB_NSTREAM] = {}; size_t Yd_cap[AAB_NSTREAM] = {};       // and their d/dR_a
     hipStream_t aab_side[AAB_NSTREAM - 1] = {};   // default priority, non-blocking
+    int64_t aab_chunk = (int64_t)1 << 17;          // triples per (class, chunk) work item
     hipEvent_t aab_ev[AAB_NSTREAM] = {};          // [0] fork from the context stream, [w] join of side stream w
     double *stats = nullptr; size_t stats_cap = 0;  // per-shell screening statistics
+    // family sets (shg_set_pairs): folded weights, radial-scratch sizes and
+    // offsets, spherical functions per set, l-block items, radial scratch
+    double *set_w = nullptr; size_t set_w_cap = 0;
+    int64_t *set_osz = nullptr; size_t set_osz_cap = 0;
+    int64_t *set_nsgf = nullptr; size_t set_nsgf_cap = 0;
+    shg::SetItem *set_items = nullptr; size_t set_items_cap = 0;
+    double *set_O = nullptr; size_t set_O_cap = 0;
     int32_t *bins = nullptr;         // [2][NBINS_MAX + 1]: histogram, then cursors
     int32_t *err = nullptr;          // device error flag
     int32_t *host_rb = nullptr;      // pinned read-back: class starts + error
@@ -127,10 +136,14 @@ void r2n_radial_range(hipStream_t s, int cls, bool deriv, const shg_shells *sh, 
                       const int32_t *order, const double *w, int nr, double *T, int64_t start, int64_t count);
 int gcoulomb_pairs(shg_ctx *c, const char *what, double omega, const shg_shells *sh, const int32_t *pairs, int64_t n,
                    const int64_t *out_off, double *out, double *dout);
-// screening decisions (shg_screen.hip): keep[i] = 0 if pair i may be skipped
-// (with deriv the bound also covers the d/dR_a elements and the model is not
-// consulted); work: n * 15 floats of scratch
-int screen_pairs(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
-                 int deriv, double tau, shg_mlp *mlp, int32_t *keep, float *work);
+// screening stage of a screened plan (shg_screen.hip): per-shell statistics
+// from the folded weights, then keep[i] (0: skip) for the n class-sorted
+// records; kernels only, graph-capturable; work: n * 15 floats with a model
+int plan_screen_enqueue(shg_ctx *c, hipStream_t s, const shg_shells *sh, const double *w, double *stats,
+                        const PairRec *rec, int64_t n, int nops, const int *ops, const double *omegas, int deriv,
+                        double tau, shg_mlp *mlp, float *work, int32_t *keep);
+size_t plan_screen_stats_doubles(int nshell);
+// whether a model predicts operator op (and, with deriv, the d/dR_a blocks too)
+bool mlp_covers(const shg_mlp *m, int op, int deriv);
 
 }  // namespace shg

@@ -24,6 +24,8 @@ struct QTile {
 // dynamic LDS limit of the persistent kernel (160 KiB minus its static LDS)
 constexpr int PERSIST_MAX_SMEM = 160 * 1024 - 256;
 
+// ntiles < 0: the number of tiles is read from counter[1] (written by an
+// earlier kernel of the same stream, e.g. a screening stage)
 template <bool D>
 __global__ __launch_bounds__(TILE_THREADS) void k_persist(TileArgs a, const QTile *__restrict__ q, int ntiles,
                                                           int *counter)
@@ -33,10 +35,11 @@ __global__ __launch_bounds__(TILE_THREADS) void k_persist(TileArgs a, const QTil
     // iteration k - 1 (after phase 1), read by all after that tile's last barrier
     __shared__ int s_t[2];
     if (threadIdx.x == 0) s_t[0] = atomicAdd(counter, 1);
+    const int nt = ntiles >= 0 ? ntiles : counter[1];
     __syncthreads();
     for (int k = 0;; ++k) {
         const int t = s_t[k & 1];
-        if (t >= ntiles) break;
+        if (t >= nt) break;
         int nxt = 0;
         if (threadIdx.x == 0) nxt = atomicAdd(counter, 1);
         const auto hand_over = [&]() {

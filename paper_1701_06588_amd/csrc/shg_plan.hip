@@ -7,15 +7,17 @@
 // shg_plan_autotune:
 //   per-class   the per-class k_tile launches of the plain path, graph-captured
 //   persistent  one k_persist launch over a tile work queue
-// A multi-operator plan (shg_plan_create_multi) evaluates several operators on
-// the pair list with one k_multi launch over the same queue.
+// A screened plan decides on every execution, on the device, which pairs are
+// evaluated: analytic bound (and learned predictor) per pair, a scan that
+// compacts the kept class-sorted records, the tile queue built from the kept
+// counts, the skipped blocks zeroed, then the persistent kernel, which reads
+// the number of tiles from device memory. Nothing is read back to the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <vector>
 
 #include "shg_ctx.h"
-#include "shg_multi.h"
 #include "shg_persist.h"
 
 using namespace shg;
@@ -30,24 +32,40 @@ struct shg_plan {
     const int64_t *out_off = nullptr;
     double *out = nullptr, *dout = nullptr;
     int deriv = 0;
-    int mode = 0;                     // 0 per-class launches, 1 persistent, 2 multi-operator
+    int mode = 0;                     // 0 per-class launches, 1 persistent
     int qorder = 1;                   // tile order: 0 heaviest first, 1 alternating ends, 2 round robin
-    int nops = 0;                     // > 0: multi-operator plan
-    MultiOps mops{};
     int32_t *order = nullptr;         // class-sorted pair ids (plan-owned)
-    PairRec *rec = nullptr;           // class-sorted pair records (plan-owned)
+    PairRec *rec = nullptr;           // class-sorted pair records (plan-owned; screened: the kept ones)
     double *w = nullptr;              // folded weights (plan-owned)
     QTile *queue = nullptr;
-    int ntiles = 0;
-    int *counter = nullptr;
+    int ntiles = 0;                   // screened: the most tiles a queue can hold
+    int *counter = nullptr;           // [0] tile counter; screened plans: the meta block below
+    // screening on the device (screened plans); meta: [0] tile counter, [1] tiles,
+    // [2] kept, [3] skipped, [META_KS + c] kept start of class c, [META_TS + k]
+    // first tile of the k-th class of the queue order
+    int screened = 0;
+    double tau = 0;
+    shg_mlp *mlp = nullptr;
+    PairRec *rec_all = nullptr;       // class-sorted records of every pair
+    int32_t *keep = nullptr;          // [n] decision per sorted position
+    int32_t *bsum = nullptr;          // [2][nblk + 1]: kept per scan block, exclusive scan
+    int32_t *skip = nullptr;          // [n] sorted positions of the skipped pairs
+    double *stats = nullptr;          // per-shell screening statistics
+    float *swork = nullptr;           // model inference scratch (n * 15 floats)
+    int64_t cls_all[NCLASS + 1] = {}; // class starts of the unscreened sorted order
     int grid = 0;
     size_t smem = 0;
     TileShape shapes[NCLASS] = {};    // per-class launches (tuned shapes)
     int64_t cls_start[NCLASS + 1] = {};
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::vector<int32_t> skipped;     // pair ids removed by screening
+    // two recorded graphs: the stage (shell preparation, radial or screening
+    // stage) and the evaluation kernels, launched back to back
+    hipGraph_t graph = nullptr, graph_k = nullptr;
+    hipGraphExec_t exec = nullptr, exec_k = nullptr;
+    // kernel timing (shg_plan_time_kernels): event pairs around the evaluation graph
+    int timing = 0;
+    std::vector<hipEvent_t> tev;      // 2 per timed execution
+    int tev_used = 0;
     double *T = nullptr;              // precomputed-monopole operators: radial terms per sorted position
     int nr = 0;                       // (a|r_a^{2n}|b): n
 };
@@ -91,7 +109,222 @@ static void plan_radial(const shg_plan *p, hipStream_t s)
     }
 }
 
-static int plan_enqueue(shg_plan *p, hipStream_t s)
+// ---------------------------------------------------------------------------
+// device screening stage of screened plans
+// ---------------------------------------------------------------------------
+constexpr int META_KS = 8, META_TS = META_KS + NCLASS + 1, META_N = META_TS + NCLASS + 1;
+constexpr int SCAN_TPB = 256, SCAN_ITEMS = 16, SCAN_BLK = SCAN_TPB * SCAN_ITEMS;
+
+// the unscreened class starts and the queue's class order (heaviest first)
+struct ScreenShape {
+    int32_t cls_all[NCLASS + 1];
+    int32_t cls_seq[NCLASS];
+    int32_t nblk;
+    int32_t qorder;   // 0 heaviest first, 1 alternating ends
+};
+
+// kept positions per scan block of SCAN_BLK sorted positions
+__global__ __launch_bounds__(SCAN_TPB) void k_keep_count(int64_t n, const int32_t *keep, int32_t *bsum)
+{
+    __shared__ int32_t red[SCAN_TPB / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_BLK;
+    int cnt = 0;
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        const int64_t i = base + (int64_t)it * SCAN_TPB + threadIdx.x;
+        if (i < n) cnt += keep[i] != 0;
+    }
+    for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// one workgroup: exclusive scan of the block counts into bscan, the kept start
+// of every class, the tile counts of the queue (classes in queue order) and
+// the meta block; clears the tile counter
+__global__ __launch_bounds__(256) void k_keep_scan(ScreenShape ss, const int32_t *keep, const int32_t *bsum,
+                                                   int32_t *bscan, int32_t *meta)
+{
+    __shared__ int32_t part[256];
+    __shared__ int32_t ks[NCLASS + 1];
+    const int t = threadIdx.x, nb = ss.nblk;
+    const int per = (nb + 255) / 256;
+    const int lo = min(nb, t * per), hi = min(nb, lo + per);
+    int32_t acc = 0;
+    for (int b = lo; b < hi; ++b) acc += bsum[b];
+    part[t] = acc;
+    __syncthreads();
+    if (t == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int32_t v = part[i];
+            part[i] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    acc = part[t];
+    for (int b = lo; b < hi; ++b) {
+        bscan[b] = acc;
+        acc += bsum[b];
+    }
+    if (t == 255) bscan[nb] = acc;
+    // kept positions before the first position of each class
+    if (t <= NCLASS) {
+        const int32_t pos = ss.cls_all[t];
+        const int b = pos / SCAN_BLK;
+        int32_t k = 0;
+        if (b < nb) {
+            const int owner = per > 0 ? b / per : 0;
+            k = part[owner];
+            for (int q = owner * per; q < b; ++q) k += bsum[q];
+            for (int32_t i = b * SCAN_BLK; i < pos; ++i) k += keep[i] != 0;
+        } else {
+            k = part[255];
+            for (int q = 255 * per; q < nb; ++q) k += bsum[q];
+        }
+        ks[t] = k;
+        meta[META_KS + t] = k;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int32_t tiles = 0;
+        for (int q = 0; q < NCLASS; ++q) {
+            const int c = ss.cls_seq[q];
+            meta[META_TS + q] = tiles;
+            tiles += (ks[c + 1] - ks[c] + 63) / 64;
+        }
+        meta[META_TS + NCLASS] = tiles;
+        meta[0] = 0;
+        meta[1] = tiles;
+        meta[2] = ks[NCLASS];
+        meta[3] = ss.cls_all[NCLASS] - ks[NCLASS];
+    }
+}
+
+// stable compaction: kept sorted position i -> rec[kept before i] = rec_all[i];
+// skipped position i -> skip[skipped before i] = i. A thread owns SCAN_ITEMS
+// consecutive positions of its block.
+__global__ __launch_bounds__(SCAN_TPB) void k_compact(int64_t n, const int32_t *keep, const int32_t *bscan,
+                                                      const PairRec *rec_all, PairRec *rec, int32_t *skip)
+{
+    __shared__ int32_t wsum[SCAN_TPB / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_BLK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int32_t flags = 0, cnt = 0;
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        const int64_t i = base + it;
+        const int k = i < n ? (keep[i] != 0) : 0;
+        flags |= k << it;
+        cnt += k;
+    }
+    // inclusive scan of the per-thread counts within the wave, then across waves
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t inc = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t v = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += v;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int32_t wbase = 0;
+    for (int q = 0; q < wv; ++q) wbase += wsum[q];
+    int32_t kept = bscan[blockIdx.x] + wbase + inc - cnt;   // kept before this thread's first position
+    int64_t skipped = base - kept;
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        const int64_t i = base + it;
+        if (i >= n) break;
+        if ((flags >> it) & 1) rec[kept++] = rec_all[i];
+        else skip[skipped++] = (int32_t)i;
+    }
+}
+
+// tile queue of the kept pairs: 64-pair tiles, classes in queue order
+// (heaviest first; alternately from the two ends with qorder 1)
+__global__ void k_build_queue(ScreenShape ss, const int32_t *meta, int max_tiles, QTile *q)
+{
+    const int ntiles = meta[1];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < max_tiles; j += gridDim.x * blockDim.x) {
+        if (j >= ntiles) break;
+        const int src = ss.qorder == 1 ? ((j & 1) ? ntiles - 1 - (j >> 1) : (j >> 1)) : j;
+        int k = 0;
+        while (k + 1 < NCLASS && meta[META_TS + k + 1] <= src) ++k;
+        const int c = ss.cls_seq[k];
+        const int32_t u = src - meta[META_TS + k];
+        const int32_t kept_c = meta[META_KS + c + 1] - meta[META_KS + c];
+        q[j] = QTile{c, min(64, kept_c - 64 * u), (int64_t)meta[META_KS + c] + 64 * (int64_t)u};
+    }
+}
+
+// skipped blocks (values and d/dR_a) set to zero, one wave per pair
+__global__ void k_zero_skipped(const int32_t *meta, const int32_t *skip, const PairRec *rec_all, const int32_t *l,
+                               double *out, double *dout)
+{
+    const int64_t nskip = meta[3];
+    const int lane = threadIdx.x & 63;
+    for (int64_t j = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; j < nskip;
+         j += (int64_t)gridDim.x * (blockDim.x / 64)) {
+        const PairRec r = rec_all[skip[j]];
+        const int sz = (2 * l[r.a] + 1) * (2 * l[r.b] + 1);
+        for (int e = lane; e < sz; e += 64) out[r.off + e] = 0.0;
+        if (dout)
+            for (int e = lane; e < 3 * sz; e += 64) dout[3 * r.off + e] = 0.0;
+    }
+}
+
+static ScreenShape plan_screen_shape(const shg_plan *p)
+{
+    ScreenShape ss{};
+    for (int c = 0; c <= NCLASS; ++c) ss.cls_all[c] = (int32_t)p->cls_all[c];
+    std::vector<std::pair<double, int>> cls_cost;
+    for (int cls = 0; cls < NCLASS; ++cls) {
+        const int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
+        cls_cost.push_back({-((double)(2 * la + 1) * (2 * lb + 1) * (p->deriv ? 4 : 1) + 4.0 * (la + lb + 1)), cls});
+    }
+    std::stable_sort(cls_cost.begin(), cls_cost.end());
+    for (int q = 0; q < NCLASS; ++q) ss.cls_seq[q] = cls_cost[q].second;
+    ss.nblk = (int32_t)((p->n + SCAN_BLK - 1) / SCAN_BLK);
+    ss.qorder = p->qorder == 0 ? 0 : 1;
+    return ss;
+}
+
+// screening stage: decisions, compaction, tile queue, skipped blocks zeroed
+static int plan_screen_stage(shg_plan *p, hipStream_t s)
+{
+    shg_ctx *c = p->ctx;
+    const int64_t n = p->n;
+    if (n == 0) return 0;
+    int rc = plan_screen_enqueue(c, s, &p->sh, p->w, p->stats, p->rec_all, n, 1, &p->op, &p->omega, p->deriv, p->tau,
+                                 p->mlp, p->swork, p->keep);
+    if (rc) return rc;
+    const ScreenShape ss = plan_screen_shape(p);
+    int32_t *bscan = p->bsum + ss.nblk + 1;
+    hipLaunchKernelGGL(k_keep_count, dim3(ss.nblk), dim3(SCAN_TPB), 0, s, n, p->keep, p->bsum);
+    hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(256), 0, s, ss, p->keep, p->bsum, bscan, p->counter);
+    hipLaunchKernelGGL(k_compact, dim3(ss.nblk), dim3(SCAN_TPB), 0, s, n, p->keep, bscan, p->rec_all, p->rec, p->skip);
+    const unsigned qgrid = (unsigned)std::max(1, std::min((p->ntiles + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_build_queue, dim3(qgrid), dim3(256), 0, s, ss, p->counter, p->ntiles, p->queue);
+    const unsigned zgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, 2048));
+    hipLaunchKernelGGL(k_zero_skipped, dim3(zgrid), dim3(256), 0, s, p->counter, p->skip, p->rec_all, p->sh.l, p->out,
+                       p->dout);
+    HIP_TRY(c, hipGetLastError());
+    return 0;
+}
+
+static void plan_launch_persist(const shg_plan *p, hipStream_t s, const TileArgs &ta)
+{
+    persist_fn f;
+    persist_occ_fn occ;
+    if (p->deriv) persist_entry_d1(&f, &occ);
+    else persist_entry_d0(&f, &occ);
+    // a screened plan's kernel reads the number of tiles from counter[1]
+    f(s, p->grid, p->smem, ta, p->queue, p->screened ? -1 : p->ntiles, p->counter);
+}
+
+// shell preparation and the stage before the evaluation kernels (radial terms
+// of the precomputed-monopole operators, or screening; the tile counter)
+static int plan_enqueue_stage(shg_plan *p, hipStream_t s)
 {
     shg_ctx *c = p->ctx;
     const shg_shells *sh = &p->sh;
@@ -99,49 +332,54 @@ static int plan_enqueue(shg_plan *p, hipStream_t s)
         hipLaunchKernelGGL(k_prep_shells, dim3((sh->nshell + 3) / 4), dim3(256), 0, s, sh->nshell, sh->l, sh->nprim,
                            sh->prim_off, sh->exps, sh->coefs, sh->nprim_total, LMAX, p->w, c->err);
     plan_radial(p, s);
+    if (p->screened) {
+        int rc = plan_screen_stage(p, s);   // also clears the tile counter
+        if (rc) return rc;
+    } else if (p->mode == 1 && p->ntiles > 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
+    }
+    HIP_TRY(c, hipGetLastError());
+    return 0;
+}
+
+// the evaluation kernels: the persistent kernel or the per-class launches
+static int plan_enqueue_kernels(shg_plan *p, hipStream_t s)
+{
     const TileArgs ta = plan_tile_args(p);
-    if (p->nops > 0) {
-        if (p->ntiles > 0) {
-            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
-            multi_fn f;
-            multi_occ_fn occ;
-            if (p->deriv) multi_entry_d1(&f, &occ);
-            else multi_entry_d0(&f, &occ);
-            f(s, p->grid, ta, p->mops, p->queue, p->ntiles, p->counter);
-        }
-    } else if (p->mode == 0) {
+    if (p->mode == 1) {
+        if (p->ntiles > 0) plan_launch_persist(p, s, ta);
+    } else {
         for (int cls = 0; cls < NCLASS; ++cls) {
             int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
             if (b1 <= b0) continue;
             tile_table(cls / (LMAX + 1))[(cls % (LMAX + 1)) * 2 + p->deriv](s, ta, b0, b1 - b0, p->shapes[cls]);
         }
-    } else if (p->ntiles > 0) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
-        persist_fn f;
-        persist_occ_fn occ;
-        if (p->deriv) persist_entry_d1(&f, &occ);
-        else persist_entry_d0(&f, &occ);
-        f(s, p->grid, p->smem, ta, p->queue, p->ntiles, p->counter);
     }
-    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(p->ctx, hipGetLastError());
     return 0;
+}
+
+static int plan_enqueue(shg_plan *p, hipStream_t s)
+{
+    int rc = plan_enqueue_stage(p, s);
+    return rc ? rc : plan_enqueue_kernels(p, s);
 }
 
 static void plan_free_graph(shg_plan *p)
 {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    p->exec = nullptr;
-    p->graph = nullptr;
+    if (p->exec_k) (void)hipGraphExecDestroy(p->exec_k);
+    if (p->graph_k) (void)hipGraphDestroy(p->graph_k);
+    p->exec = p->exec_k = nullptr;
+    p->graph = p->graph_k = nullptr;
 }
 
-static int plan_capture(shg_plan *p)
+static int capture_one(shg_plan *p, int (*enq)(shg_plan *, hipStream_t), hipGraph_t *graph, hipGraphExec_t *exec)
 {
     shg_ctx *c = p->ctx;
-    plan_free_graph(p);
-    if (!p->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     HIP_TRY(c, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = plan_enqueue(p, p->cap_stream);
+    int rc = enq(p, p->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
     if (rc) {
@@ -149,9 +387,19 @@ static int plan_capture(shg_plan *p)
         return rc;
     }
     if (e != hipSuccess) return set_err(c, SHG_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    p->graph = g;
-    HIP_TRY(c, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    *graph = g;
+    HIP_TRY(c, hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
     return 0;
+}
+
+static int plan_capture(shg_plan *p)
+{
+    shg_ctx *c = p->ctx;
+    plan_free_graph(p);
+    if (!p->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    int rc = capture_one(p, plan_enqueue_stage, &p->graph, &p->exec);
+    if (!rc) rc = capture_one(p, plan_enqueue_kernels, &p->graph_k, &p->exec_k);
+    return rc;
 }
 
 // builds the tile queue of the persistent kernels: tiles
@@ -305,7 +553,7 @@ extern "C" int shg_plan_create_r2n(shg_ctx *c, const shg_shells *sh, int nr, con
     return plan_create_impl(c, sh, PLAN_OP_R2N, 0.0, nr, pairs, n, out_off, out, dout, flags, plan);
 }
 
-// records of the pairs in `order` (after screening removed some)
+// records of the pairs in `order` (precomputed-monopole plans)
 __global__ void k_make_recs(int64_t n, const int32_t *order, const int32_t *pairs, const int64_t *out_off, PairRec *rec)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -314,64 +562,19 @@ __global__ void k_make_recs(int64_t n, const int32_t *order, const int32_t *pair
     rec[i] = PairRec{pairs[2 * p], pairs[2 * p + 1], out_off[p]};
 }
 
-__global__ void k_zero_blocks(int64_t ns, const int32_t *ids, const int32_t *pairs, const int32_t *l,
-                              const int64_t *out_off, double *out, double *dout)
-{
-    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-    if (i >= ns) return;
-    const int p = ids[i];
-    const int sz = (2 * l[pairs[2 * (int64_t)p]] + 1) * (2 * l[pairs[2 * (int64_t)p + 1]] + 1);
-    const int64_t off = out_off[p];
-    for (int e = threadIdx.x % 64; e < sz; e += 64) out[off + e] = 0.0;
-    if (dout)
-        for (int e = threadIdx.x % 64; e < 3 * sz; e += 64) dout[3 * off + e] = 0.0;
-}
-
-// keeps the pairs with hkeep[id] != 0: stable compaction of the class-sorted
-// order and records, skipped ids collected, their blocks zeroed in every
-// output of the plan, tile queue rebuilt
-static int plan_compact(shg_plan *p, const std::vector<int32_t> &hkeep, const std::vector<int32_t> &horder,
-                        int64_t *nskip_out)
+// reads the decision of the last execution back: kept and skipped counts and
+// the kept class starts (synchronises the context stream)
+static int plan_read_meta(const shg_plan *p, int64_t *kept, int64_t *skipped, int64_t *ks)
 {
     shg_ctx *c = p->ctx;
-    std::vector<int32_t> korder, skipped;
-    korder.reserve(p->n);
-    int64_t new_start[NCLASS + 1];
-    for (int cls = 0; cls < NCLASS; ++cls) {
-        new_start[cls] = (int64_t)korder.size();
-        for (int64_t q = p->cls_start[cls]; q < p->cls_start[cls + 1]; ++q) {
-            int32_t id = horder[q];
-            if (hkeep[id]) korder.push_back(id);
-            else skipped.push_back(id);
-        }
-    }
-    new_start[NCLASS] = (int64_t)korder.size();
-    const int64_t nskip = (int64_t)skipped.size();
-    p->skipped = skipped;
-    if (!korder.empty()) {
-        const int64_t nk = (int64_t)korder.size();
-        HIP_TRY(c, hipMemcpy(p->order, korder.data(), nk * sizeof(int32_t), hipMemcpyHostToDevice));
-        hipLaunchKernelGGL(k_make_recs, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, c->stream, nk, p->order,
-                           p->pairs, p->out_off, p->rec);
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-    }
-    for (int cls = 0; cls <= NCLASS; ++cls) p->cls_start[cls] = new_start[cls];
-    if (nskip > 0) {
-        int32_t *ids = nullptr;
-        HIP_TRY(c, hipMalloc((void **)&ids, nskip * sizeof(int32_t)));
-        HIP_TRY(c, hipMemcpy(ids, skipped.data(), nskip * sizeof(int32_t), hipMemcpyHostToDevice));
-        const int nout = p->nops > 0 ? p->nops : 1;
-        for (int o = 0; o < nout; ++o) {
-            double *out = p->nops > 0 ? p->mops.out[o] : p->out;
-            double *dout = p->nops > 0 ? p->mops.dout[o] : p->dout;
-            hipLaunchKernelGGL(k_zero_blocks, dim3((unsigned)((nskip + 3) / 4)), dim3(256), 0, c->stream, nskip, ids,
-                               p->pairs, p->sh.l, p->out_off, out, dout);
-        }
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        (void)hipFree(ids);
-    }
-    *nskip_out = nskip;
-    return plan_build_queue(p);
+    int32_t m[META_N];
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(m, p->counter, sizeof(m), hipMemcpyDeviceToHost));
+    if (kept) *kept = m[2];
+    if (skipped) *skipped = m[3];
+    if (ks)
+        for (int cls = 0; cls <= NCLASS; ++cls) ks[cls] = m[META_KS + cls];
+    return 0;
 }
 
 extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op op, double omega,
@@ -379,153 +582,123 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
                                         double *dout, unsigned flags, double tau, shg_mlp *mlp, shg_plan **plan,
                                         int64_t *n_skipped)
 {
+    const char *what = "shg_plan_create_screened";
     if (!c || !plan) return SHG_EINVAL;
     *plan = nullptr;
-    if (!(tau > 0.0)) return set_err(c, SHG_EINVAL, "shg_plan_create_screened: tau must be positive");
+    if (!(tau > 0.0) || !(tau < 1e300)) return set_err(c, SHG_EINVAL, "%s: tau must be positive and finite", what);
+    if ((int)op < 0 || (int)op > 4) return set_err(c, SHG_EINVAL, "%s: operator %d cannot be screened", what, (int)op);
+    if (flags & SHG_PLAN_NO_GRAPH) return set_err(c, SHG_EINVAL, "%s: screened plans are always recorded", what);
     shg_plan *p = nullptr;
-    int rc = shg_plan_create(c, sh, op, omega, pairs, n, out_off, out, dout, flags | SHG_PLAN_NO_GRAPH, &p);
+    int rc = shg_plan_create(c, sh, op, omega, pairs, n, out_off, out, dout,
+                             (flags | SHG_PLAN_PERSISTENT | SHG_PLAN_NO_GRAPH), &p);
     if (rc) return rc;
     auto fail = [&](int code) { shg_plan_destroy(p); return code; };
-    int64_t nskip = 0;
+    if (p->smem > (size_t)PERSIST_MAX_SMEM)
+        return fail(set_err(c, SHG_EINVAL, "%s: the persistent kernel cannot take these tiles", what));
+    p->screened = 1;
+    p->mode = 1;
+    p->tau = tau;
+    p->mlp = mlp;
+    for (int cls = 0; cls <= NCLASS; ++cls) p->cls_all[cls] = p->cls_start[cls];
+    const int64_t nb = (n + SCAN_BLK - 1) / SCAN_BLK;
+    hipError_t e = hipSuccess;
     if (n > 0) {
-        int32_t *keep = nullptr;
-        float *work = nullptr;
-        HIP_TRY(c, hipMalloc((void **)&keep, n * sizeof(int32_t)));
-        if (hipMalloc((void **)&work, (size_t)n * 15 * sizeof(float)) != hipSuccess) {
-            (void)hipFree(keep);
-            return fail(set_err(c, SHG_ENOMEM, "shg_plan_create_screened: out of device memory"));
-        }
-        rc = screen_pairs(c, sh, op, omega, pairs, n, p->deriv, tau, mlp, keep, work);
-        std::vector<int32_t> hkeep(n), horder(n);
-        if (!rc && (hipMemcpy(hkeep.data(), keep, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
-                    hipMemcpy(horder.data(), p->order, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess))
-            rc = set_err(c, SHG_EDEVICE, "shg_plan_create_screened: read-back failed");
-        (void)hipFree(work);
-        (void)hipFree(keep);
-        if (rc) return fail(rc);
-        if ((rc = plan_compact(p, hkeep, horder, &nskip))) return fail(rc);
+        e = hipMalloc((void **)&p->rec_all, n * sizeof(PairRec));
+        if (e == hipSuccess) e = hipMalloc((void **)&p->keep, n * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&p->skip, n * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&p->bsum, 2 * (nb + 1) * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&p->stats, plan_screen_stats_doubles(sh->nshell) * sizeof(double));
+        if (e == hipSuccess && mlp) e = hipMalloc((void **)&p->swork, (size_t)n * 15 * sizeof(float));
+        if (e == hipSuccess) e = hipMemcpy(p->rec_all, p->rec, n * sizeof(PairRec), hipMemcpyDeviceToDevice);
     }
-    if (!(flags & SHG_PLAN_NO_GRAPH) && (rc = plan_capture(p))) return fail(rc);
-    if (n_skipped) *n_skipped = nskip;
+    if (e == hipSuccess) {
+        (void)hipFree(p->counter);
+        p->counter = nullptr;
+        e = hipMalloc((void **)&p->counter, META_N * sizeof(int32_t));
+    }
+    if (e != hipSuccess) return fail(set_err(c, SHG_ENOMEM, "%s: %s", what, hipGetErrorString(e)));
+    if ((rc = plan_capture(p))) return fail(rc);
+    // the first execution zeroes the skipped blocks (the plain evaluation of the
+    // creation wrote every block) and gives the skip count
+    if ((rc = shg_plan_execute(p))) return fail(rc);
+    int64_t ns = 0;
+    if ((rc = plan_read_meta(p, nullptr, &ns, nullptr))) return fail(rc);
+    if (n_skipped) *n_skipped = ns;
     *plan = p;
     return 0;
 }
 
-extern "C" int shg_plan_create_multi(shg_ctx *c, const shg_shells *sh, int nops, const shg_op *ops,
-                                     const double *omegas, const int32_t *pairs, int64_t n, const int64_t *out_off,
-                                     double *const *outs, double *const *douts, double tau, shg_plan **plan,
-                                     int64_t *n_skipped)
-{
-    const char *what = "shg_plan_create_multi";
-    if (!c || !plan) return SHG_EINVAL;
-    *plan = nullptr;
-    if (nops < 1 || nops > MULTI_MAX) return set_err(c, SHG_EINVAL, "%s: 1 to %d operators", what, MULTI_MAX);
-    if (!ops || !omegas || !outs) return set_err(c, SHG_EINVAL, "%s: NULL pointer argument", what);
-    if (tau < 0.0 || !(tau < 1e300)) return set_err(c, SHG_EINVAL, "%s: tau must be >= 0 and finite", what);
-    const bool deriv = douts != nullptr;
-    for (int o = 0; o < nops; ++o)
-        if (!outs[o] || (deriv && !douts[o])) return set_err(c, SHG_EINVAL, "%s: NULL output pointer", what);
-    for (int o = 0; o < nops; ++o)
-        if ((int)ops[o] < 0 || (int)ops[o] > 4)
-            return set_err(c, SHG_EINVAL, "%s: operator %d is not available in plans", what, (int)ops[o]);
-    // every operator once through the plain path: validation and the exact blocks
-    int rc = 0;
-    for (int o = 0; o < nops; ++o) {
-        rc = deriv ? shg_pairs_deriv(c, sh, ops[o], omegas[o], pairs, n, out_off, outs[o], douts[o])
-                   : shg_pairs(c, sh, ops[o], omegas[o], pairs, n, out_off, outs[o]);
-        if (rc) return rc;
-    }
-    shg_plan *p = nullptr;
-    rc = shg_plan_create(c, sh, ops[0], omegas[0], pairs, n, out_off, outs[0], deriv ? douts[0] : nullptr,
-                         SHG_PLAN_NO_GRAPH, &p);
-    if (rc) return rc;
-    auto fail = [&](int code) { shg_plan_destroy(p); return code; };
-    p->nops = nops;
-    p->mode = 2;
-    p->mops.nops = nops;
-    for (int o = 0; o < MULTI_MAX; ++o) {
-        const int oo = o < nops ? o : 0;
-        p->mops.op[o] = (int)ops[oo];
-        p->mops.omega[o] = omegas[oo];
-        p->mops.out[o] = outs[oo];
-        p->mops.dout[o] = deriv ? douts[oo] : nullptr;
-    }
-    int64_t nskip = 0;
-    if (tau > 0.0 && n > 0) {
-        // a pair is skipped only when every operator's bound is below tau
-        int32_t *keep = nullptr;
-        float *work = nullptr;
-        HIP_TRY(c, hipMalloc((void **)&keep, n * sizeof(int32_t)));
-        if (hipMalloc((void **)&work, (size_t)n * 15 * sizeof(float)) != hipSuccess) {
-            (void)hipFree(keep);
-            return fail(set_err(c, SHG_ENOMEM, "%s: out of device memory", what));
-        }
-        std::vector<int32_t> hkeep(n, 0), tmp(n), horder(n);
-        for (int o = 0; o < nops && !rc; ++o) {
-            rc = screen_pairs(c, sh, ops[o], omegas[o], pairs, n, p->deriv, tau, nullptr, keep, work);
-            if (!rc && hipMemcpy(tmp.data(), keep, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-                rc = set_err(c, SHG_EDEVICE, "%s: read-back failed", what);
-            for (int64_t i = 0; i < n && !rc; ++i) hkeep[i] |= tmp[i];
-        }
-        if (!rc && hipMemcpy(horder.data(), p->order, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-            rc = set_err(c, SHG_EDEVICE, "%s: read-back failed", what);
-        (void)hipFree(work);
-        (void)hipFree(keep);
-        if (rc) return fail(rc);
-        if ((rc = plan_compact(p, hkeep, horder, &nskip))) return fail(rc);
-    }
-    multi_fn f;
-    multi_occ_fn occ;
-    if (p->deriv) multi_entry_d1(&f, &occ);
-    else multi_entry_d0(&f, &occ);
-    hipDeviceProp_t prop;
-    HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
-    p->grid = std::max(1, std::min(p->ntiles, prop.multiProcessorCount * occ()));
-    if ((rc = plan_capture(p))) return fail(rc);
-    if (n_skipped) *n_skipped = nskip;
-    *plan = p;
-    return 0;
-}
+constexpr int PLAN_TIMED_MAX = 1024;
 
 extern "C" int shg_plan_execute(shg_plan *p)
 {
     if (!p) return SHG_EINVAL;
     shg_ctx *c = p->ctx;
-    if (p->exec) {
-        HIP_TRY(c, hipGraphLaunch(p->exec, c->stream));
-        return 0;
+    const bool timed = p->timing && p->tev_used < PLAN_TIMED_MAX;
+    if (timed && (size_t)(2 * p->tev_used + 2) > p->tev.size()) {
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t ev;
+            HIP_TRY(c, hipEventCreate(&ev));
+            p->tev.push_back(ev);
+        }
     }
-    return plan_enqueue(p, c->stream);
+    if (p->exec) HIP_TRY(c, hipGraphLaunch(p->exec, c->stream));
+    else if (int rc = plan_enqueue_stage(p, c->stream)) return rc;
+    if (timed) HIP_TRY(c, hipEventRecord(p->tev[2 * p->tev_used], c->stream));
+    if (p->exec_k) HIP_TRY(c, hipGraphLaunch(p->exec_k, c->stream));
+    else if (int rc = plan_enqueue_kernels(p, c->stream)) return rc;
+    if (timed) {
+        HIP_TRY(c, hipEventRecord(p->tev[2 * p->tev_used + 1], c->stream));
+        ++p->tev_used;
+    }
+    return 0;
+}
+
+extern "C" int shg_plan_time_kernels(shg_plan *p, int on)
+{
+    if (!p) return SHG_EINVAL;
+    p->timing = on ? 1 : 0;
+    p->tev_used = 0;
+    return 0;
+}
+
+extern "C" int shg_plan_kernel_time(shg_plan *p, double *ms_sum, int64_t *executions)
+{
+    if (!p || !ms_sum || !executions) return SHG_EINVAL;
+    shg_ctx *c = p->ctx;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double tot = 0;
+    for (int i = 0; i < p->tev_used; ++i) {
+        float ms = 0;
+        HIP_TRY(c, hipEventElapsedTime(&ms, p->tev[2 * i], p->tev[2 * i + 1]));
+        tot += ms;
+    }
+    *ms_sum = tot;
+    *executions = p->tev_used;
+    p->tev_used = 0;
+    return 0;
 }
 
 extern "C" int shg_plan_set_mode(shg_plan *p, int persistent)
 {
     if (!p) return SHG_EINVAL;
-    if (p->nops > 0) return set_err(p->ctx, SHG_EINVAL, "plan: a multi-operator plan has one mode");
+    if (p->screened && !persistent)
+        return set_err(p->ctx, SHG_EINVAL, "plan: a screened plan runs the persistent kernel only");
     if (persistent && p->smem > (size_t)PERSIST_MAX_SMEM)
         return set_err(p->ctx, SHG_EINVAL, "plan: tile shapes need more LDS than the persistent kernel allows");
     p->mode = persistent ? 1 : 0;
-    if (p->graph || p->exec) {
+    if (p->exec) {
         HIP_TRY(p->ctx, hipStreamSynchronize(p->ctx->stream));
         return plan_capture(p);
     }
     return 0;
 }
 
-extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms);
-
 extern "C" int shg_plan_autotune(shg_plan *p, int reps, double *ms_per_class, double *ms_persistent)
 {
     if (!p) return SHG_EINVAL;
     shg_ctx *c = p->ctx;
     if (reps < 1) reps = 1;
-    if (p->nops > 0) {   // one mode: report its time
-        double ms = 0;
-        int rc = shg_plan_kernel_ms(p, reps, &ms);
-        if (ms_per_class) *ms_per_class = -1.0;
-        if (ms_persistent) *ms_persistent = ms;
-        return rc;
-    }
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
@@ -543,14 +716,17 @@ extern "C" int shg_plan_autotune(shg_plan *p, int reps, double *ms_per_class, do
         return 0;
     };
     float t_class = 0, t_pers = 0;
-    int rc = time_mode(0, &t_class);
-    if (rc) return rc;
+    int rc = 0;
+    // a screened plan runs the persistent kernel over a queue built on the
+    // device in one of the first two orders
+    if (!p->screened && (rc = time_mode(0, &t_class))) return rc;
     const bool can_persist = p->smem <= (size_t)PERSIST_MAX_SMEM;
     if (can_persist) {
         // the persistent kernel with each tile order of the queue
         int best_q = p->qorder;
         float best = 0;
-        for (int qo = 0; qo < 3; ++qo) {
+        const int norders = p->screened ? 2 : 3;
+        for (int qo = 0; qo < norders; ++qo) {
             p->qorder = qo;
             if ((rc = plan_build_queue(p))) return rc;
             float t = 0;
@@ -566,10 +742,14 @@ extern "C" int shg_plan_autotune(shg_plan *p, int reps, double *ms_per_class, do
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (ms_per_class) *ms_per_class = t_class;
+    if (ms_per_class) *ms_per_class = p->screened ? -1.0 : t_class;
     if (ms_persistent) *ms_persistent = can_persist ? t_pers : -1.0;
-    p->mode = (can_persist && t_pers < t_class) ? 1 : 0;
-    if (p->graph || p->exec) return plan_capture(p);
+    p->mode = p->screened || (can_persist && t_pers < t_class) ? 1 : 0;
+    if (p->exec) {
+        if ((rc = plan_capture(p))) return rc;
+    }
+    // a screened plan leaves the outputs of its last decision in place
+    if (p->screened) return shg_plan_execute(p);
     return 0;
 }
 
@@ -577,28 +757,57 @@ extern "C" int shg_plan_mode(const shg_plan *p) { return p ? p->mode : SHG_EINVA
 
 extern "C" int shg_plan_tile_order(const shg_plan *p) { return p ? p->qorder : SHG_EINVAL; }
 
-// ids of the pairs a screened plan skips (host array of capacity cap); returns
-// their number (the full count even when cap is smaller)
+extern "C" int shg_plan_set_tile_order(shg_plan *p, int order)
+{
+    if (!p) return SHG_EINVAL;
+    if (order < 0 || order > (p->screened ? 1 : 2))
+        return set_err(p->ctx, SHG_EINVAL, "plan: tile order %d not available for this plan", order);
+    HIP_TRY(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    p->qorder = order;
+    int rc = plan_build_queue(p);
+    if (!rc && p->exec) rc = plan_capture(p);
+    return rc;
+}
+
+// ids of the pairs the last execution of a screened plan skipped (host array
+// of capacity cap; synchronises the context stream); returns their number
+// (the full count even when cap is smaller); 0 for unscreened plans
 extern "C" int64_t shg_plan_skipped(const shg_plan *p, int32_t *ids, int64_t cap)
 {
     if (!p) return SHG_EINVAL;
-    int64_t n = (int64_t)p->skipped.size();
-    if (ids)
-        for (int64_t i = 0; i < n && i < cap; ++i) ids[i] = p->skipped[i];
-    return n;
+    if (!p->screened || p->n == 0) return 0;
+    int64_t ns = 0;
+    int rc = plan_read_meta(p, nullptr, &ns, nullptr);
+    if (rc) return rc;
+    if (ids && cap > 0 && ns > 0) {
+        const int64_t m = std::min(ns, cap);
+        std::vector<int32_t> pos(m), order(p->n);
+        if (hipMemcpy(pos.data(), p->skip, m * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(order.data(), p->order, p->n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return set_err(p->ctx, SHG_EDEVICE, "shg_plan_skipped: read-back failed");
+        for (int64_t i = 0; i < m; ++i) ids[i] = order[pos[i]];
+    }
+    return ns;
 }
 
 // kept pairs and their algorithmic bytes (output values [+ d/dR_a] + 8 bytes of
-// pair indices + 8 bytes of offset per pair), host pointers
+// pair indices + 8 bytes of offset per pair), host pointers; a screened plan
+// reports its last execution (synchronises the context stream)
 extern "C" int shg_plan_stats(const shg_plan *p, int64_t *kept, int64_t *alg_bytes)
 {
     if (!p || !kept || !alg_bytes) return SHG_EINVAL;
+    int64_t starts[NCLASS + 1];
+    for (int cls = 0; cls <= NCLASS; ++cls) starts[cls] = p->cls_start[cls];
+    if (p->screened && p->n > 0) {
+        int rc = plan_read_meta(p, nullptr, nullptr, starts);
+        if (rc) return rc;
+    }
     int64_t k = 0, b = 0;
     for (int cls = 0; cls < NCLASS; ++cls) {
-        int64_t cnt = p->cls_start[cls + 1] - p->cls_start[cls];
+        int64_t cnt = starts[cls + 1] - starts[cls];
         int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
         k += cnt;
-        b += cnt * ((int64_t)8 * (2 * la + 1) * (2 * lb + 1) * (p->deriv ? 4 : 1) * (p->nops > 0 ? p->nops : 1) + 16);
+        b += cnt * ((int64_t)8 * (2 * la + 1) * (2 * lb + 1) * (p->deriv ? 4 : 1) + 16);
     }
     *kept = k;
     *alg_bytes = b;
@@ -606,8 +815,9 @@ extern "C" int shg_plan_stats(const shg_plan *p, int64_t *kept, int64_t *alg_byt
 }
 
 // average duration (ms) of the evaluation kernels alone (persistent kernel or
-// the per-class launches, without the shell preparation), timed with HIP events
-// over `reps` enqueues on the ctx stream; synchronous
+// the per-class launches, without the shell preparation or screening stage),
+// timed with HIP events over `reps` enqueues on the ctx stream; synchronous. A
+// screened plan runs its kernel on the tile queue of its last execution.
 extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
 {
     if (!p || !ms || reps < 1) return SHG_EINVAL;
@@ -621,18 +831,8 @@ extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
         if (p->mode >= 1) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, 1);
         HIP_TRY(c, hipEventRecord(e0, c->stream));
         plan_radial(p, c->stream);
-        if (p->nops > 0) {
-            multi_fn f;
-            multi_occ_fn occ;
-            if (p->deriv) multi_entry_d1(&f, &occ);
-            else multi_entry_d0(&f, &occ);
-            if (p->ntiles > 0) f(c->stream, p->grid, ta, p->mops, p->queue, p->ntiles, p->counter);
-        } else if (p->mode == 1) {
-            persist_fn f;
-            persist_occ_fn occ;
-            if (p->deriv) persist_entry_d1(&f, &occ);
-            else persist_entry_d0(&f, &occ);
-            if (p->ntiles > 0) f(c->stream, p->grid, p->smem, ta, p->queue, p->ntiles, p->counter);
+        if (p->mode == 1) {
+            if (p->ntiles > 0) plan_launch_persist(p, c->stream, ta);
         } else {
             for (int cls = 0; cls < NCLASS; ++cls) {
                 int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
@@ -658,6 +858,7 @@ extern "C" void shg_plan_destroy(shg_plan *p)
     if (!p) return;
     if (p->ctx) (void)hipStreamSynchronize(p->ctx->stream);
     plan_free_graph(p);
+    for (hipEvent_t ev : p->tev) (void)hipEventDestroy(ev);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     (void)hipFree(p->order);
     (void)hipFree(p->rec);
@@ -665,5 +866,11 @@ extern "C" void shg_plan_destroy(shg_plan *p)
     (void)hipFree(p->w);
     (void)hipFree(p->queue);
     (void)hipFree(p->counter);
+    (void)hipFree(p->rec_all);
+    (void)hipFree(p->keep);
+    (void)hipFree(p->skip);
+    (void)hipFree(p->bsum);
+    (void)hipFree(p->stats);
+    (void)hipFree(p->swork);
     delete p;
 }

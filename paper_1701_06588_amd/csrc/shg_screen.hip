@@ -85,14 +85,14 @@ struct BoundTab {
 
 __device__ __forceinline__ double dfact_d(int n) { double f = 1; for (int i = n; i > 1; i -= 2) f *= i; return f; }
 
-// log10 of the analytic bound and the 12 features of one pair
-__global__ void k_bound_features(int64_t n, const int32_t *pairs, const double *center, const int32_t *l,
-                                 const double *st, int op, double omega, int deriv, BoundTab bt, float *feat,
-                                 float *logb)
+// Analytic bound of one pair (a, b): returns the bound on max|block| and, with
+// deriv, on the d/dR_a elements too (their maximum); *vbound receives the
+// value bound alone. *R_out and *rmin_out receive R and the smallest reduced
+// exponent (features).
+__device__ double pair_bound(int a, int b, const double *center, const int32_t *l, const double *st, int op,
+                             double omega, int deriv, const BoundTab &bt, double *vbound, double *R_out,
+                             double *rmin_out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int a = pairs[2 * i], b = pairs[2 * i + 1];
     const int la = l[a], lb = l[b];
     const double X0 = center[3 * a] - center[3 * b], X1 = center[3 * a + 1] - center[3 * b + 1],
                  X2 = center[3 * a + 2] - center[3 * b + 2];
@@ -131,29 +131,86 @@ __global__ void k_bound_features(int64_t n, const int32_t *pairs, const double *
             dbound += t * bt.cq[la][lb][j];
         }
     }
-    const double vbound = bound;
-    if (deriv) bound = fmax(bound, dbound);
-    const double lb10 = bound > 0 ? log10(bound) : -300.0;
-    logb[i] = (float)fmax(lb10, -300.0);
-    const double lv10 = vbound > 0 ? log10(vbound) : -300.0;
-    float *f = feat + i * NF;
-    f[0] = (float)la;
-    f[1] = (float)lb;
+    *vbound = bound;
+    *R_out = R;
+    *rmin_out = rmin;
+    return deriv ? fmax(bound, dbound) : bound;
+}
+
+__device__ __forceinline__ float clamped_log10(double x, double lo) { return (float)fmax(x > 0 ? log10(x) : lo, lo); }
+
+// the 12 screening features of pair (a, b); `bnd` is the bound of the outputs
+// being screened (values, or values and d/dR_a)
+__device__ void pair_features(int a, int b, const int32_t *l, const double *st, int op, double omega, double R,
+                              double rmin, double bnd, float *f)
+{
+    const double *sa = st + (size_t)a * STAT, *sb = st + (size_t)b * STAT;
+    f[0] = (float)l[a];
+    f[1] = (float)l[b];
     f[2] = (float)log10(sa[0]);
     f[3] = (float)log10(sa[1]);
     f[4] = (float)log10(sb[0]);
     f[5] = (float)log10(sb[1]);
     f[6] = (float)R;
-    f[7] = (float)log10(1.0 + rmin * R2);
-    f[8] = (float)fmax(lv10, -40.0);
-    f[9] = op == OP_ERFC ? 1.0f : 0.0f;
+    f[7] = (float)log10(1.0 + rmin * R * R);
+    f[8] = clamped_log10(bnd, -40.0);
+    f[9] = (float)op;
     f[10] = (op == OP_ERF || op == OP_ERFC) ? (float)(omega * R) : 0.0f;
     f[11] = (float)log10(sa[2] * sb[2]);
 }
 
-// log10 max|block| (clamped at -30) of evaluated blocks: the training target
+// log10 of the analytic bound and the 12 features of one pair
+__global__ void k_bound_features(int64_t n, const int32_t *pairs, const double *center, const int32_t *l,
+                                 const double *st, int op, double omega, int deriv, BoundTab bt, float *feat,
+                                 float *logb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = pairs[2 * i], b = pairs[2 * i + 1];
+    double vb, R, rmin;
+    const double bound = pair_bound(a, b, center, l, st, op, omega, deriv, bt, &vb, &R, &rmin);
+    logb[i] = clamped_log10(bound, -300.0);
+    pair_features(a, b, l, st, op, omega, R, rmin, bound, feat + i * NF);
+}
+
+// In-plan screening over class-sorted positions (records rec): keep[i] = 1 when
+// the bound of any of the plan's operators reaches tau; with a model (one
+// operator) the features and log10 bound are written for inference and k_keep
+// makes the decision.
+struct PlanOps {
+    int nops, op[5];
+    double omega[5];
+};
+
+// fderiv: the features (log10 bound) are those of a model trained on targets
+// with (1) or without (0) the d/dR_a blocks, whatever the plan evaluates
+__global__ void k_plan_bound(int64_t n, const PairRec *rec, const double *center, const int32_t *l, const double *st,
+                             PlanOps po, int deriv, int fderiv, BoundTab bt, double tau, int32_t *keep, float *feat,
+                             float *logb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const PairRec r = rec[i];
+    int k = 0;
+    for (int o = 0; o < po.nops; ++o) {
+        double vb, R, rmin;
+        const double bound = pair_bound(r.a, r.b, center, l, st, po.op[o], po.omega[o], deriv, bt, &vb, &R, &rmin);
+        k |= !(bound < tau);
+        if (feat) {
+            logb[i] = clamped_log10(bound, -300.0);
+            double fb = bound;
+            if (fderiv != deriv)
+                fb = pair_bound(r.a, r.b, center, l, st, po.op[o], po.omega[o], fderiv, bt, &vb, &R, &rmin);
+            pair_features(r.a, r.b, l, st, po.op[o], po.omega[o], R, rmin, fb, feat + i * NF);
+        }
+    }
+    keep[i] = k;
+}
+
+// log10 max|block| (clamped at -30) of evaluated blocks, over the values and,
+// with dout, their d/dR_a blocks too: the training target
 __global__ void k_block_logmax(int64_t n, const int32_t *pairs, const int32_t *l, const int64_t *out_off,
-                               const double *out, float *y)
+                               const double *out, const double *dout, float *y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -161,6 +218,8 @@ __global__ void k_block_logmax(int64_t n, const int32_t *pairs, const int32_t *l
     const int sz = (2 * la + 1) * (2 * lb + 1);
     double m = 0;
     for (int e = 0; e < sz; ++e) m = fmax(m, fabs(out[out_off[i] + e]));
+    if (dout)
+        for (int e = 0; e < 3 * sz; ++e) m = fmax(m, fabs(dout[3 * out_off[i] + e]));
     y[i] = (float)fmax(m > 0 ? log10(m) : -30.0, -30.0);
 }
 
@@ -517,6 +576,10 @@ struct shg_mlp {
     uint16_t *wb = nullptr;                                         // bf16 working copy (packed)
     MlpNorm norm{};
     float margin = 0.0f;
+    // what the model predicts: the operators (bit per shg_op) and whether the
+    // targets include the d/dR_a blocks; plans consult it only within this scope
+    uint32_t ops_mask = (1u << SHG_COULOMB) | (1u << SHG_ERFC);
+    int deriv_targets = 0;
     int step = 0;
     TrainBuf tb{};
     int tb_cap = 0;
@@ -607,6 +670,14 @@ extern "C" int shg_mlp_set_margin(shg_mlp *m, float margin)
     return 0;
 }
 
+extern "C" int shg_mlp_set_scope(shg_mlp *m, uint32_t ops_mask, int deriv_targets)
+{
+    if (!m || ops_mask == 0 || (ops_mask >> 5) != 0) return SHG_EINVAL;
+    m->ops_mask = ops_mask;
+    m->deriv_targets = deriv_targets ? 1 : 0;
+    return 0;
+}
+
 static int ensure_tb(shg_mlp *m, int B)
 {
     if (B <= m->tb_cap) return 0;
@@ -688,6 +759,9 @@ extern "C" int shg_mlp_predict(shg_mlp *m, const float *feat, int64_t n, float *
     return mlp_predict(m, feat, n, pred, in_range);
 }
 
+// model file: magic "SHGMLP02", 9217 fp32 parameters, the standardisation, the
+// margin, the operator mask and the derivative-target flag ("SHGMLP01" files,
+// without the last two, predict Coulomb and erfc values)
 extern "C" int shg_mlp_save(shg_mlp *m, const char *path)
 {
     if (!m || !path) return SHG_EINVAL;
@@ -696,13 +770,13 @@ extern "C" int shg_mlp_save(shg_mlp *m, const char *path)
     if (rc) return rc;
     FILE *f = fopen(path, "wb");
     if (!f) return set_err(m->ctx, SHG_EINVAL, "shg_mlp_save: cannot open %s", path);
-    const char magic[8] = {'S', 'H', 'G', 'M', 'L', 'P', '0', '1'};
-    fwrite(magic, 1, 8, f);
-    fwrite(p.data(), sizeof(float), NPARAM, f);
-    fwrite(&m->norm, sizeof(MlpNorm), 1, f);
-    fwrite(&m->margin, sizeof(float), 1, f);
-    fclose(f);
-    return 0;
+    const char magic[8] = {'S', 'H', 'G', 'M', 'L', 'P', '0', '2'};
+    const uint32_t scope[2] = {m->ops_mask, (uint32_t)m->deriv_targets};
+    bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(p.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM &&
+              fwrite(&m->norm, sizeof(MlpNorm), 1, f) == 1 && fwrite(&m->margin, sizeof(float), 1, f) == 1 &&
+              fwrite(scope, sizeof(uint32_t), 2, f) == 2;
+    ok &= fclose(f) == 0;
+    return ok ? 0 : set_err(m->ctx, SHG_EINVAL, "shg_mlp_save: write to %s failed", path);
 }
 
 extern "C" int shg_mlp_load(shg_mlp *m, const char *path)
@@ -714,15 +788,19 @@ extern "C" int shg_mlp_load(shg_mlp *m, const char *path)
     std::vector<float> p(NPARAM);
     MlpNorm nm;
     float margin;
-    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "SHGMLP01", 8) == 0 &&
+    uint32_t scope[2] = {(1u << SHG_COULOMB) | (1u << SHG_ERFC), 0};
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "SHGMLP0", 7) == 0 && (magic[7] == '1' || magic[7] == '2') &&
               fread(p.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM && fread(&nm, sizeof(nm), 1, f) == 1 &&
               fread(&margin, sizeof(float), 1, f) == 1;
+    if (ok && magic[7] == '2') ok = fread(scope, sizeof(uint32_t), 2, f) == 2 && scope[0] != 0 && (scope[0] >> 5) == 0;
     fclose(f);
     if (!ok) return set_err(m->ctx, SHG_EINVAL, "shg_mlp_load: %s is not a model file", path);
     int rc = shg_mlp_params(m, nullptr, p.data());
     if (rc) return rc;
     m->norm = nm;
     m->margin = margin;
+    m->ops_mask = scope[0];
+    m->deriv_targets = scope[1] ? 1 : 0;
     return 0;
 }
 
@@ -755,12 +833,13 @@ extern "C" int shg_screen_features(shg_ctx *c, const shg_shells *sh, shg_op op, 
 }
 
 extern "C" int shg_block_logmax(shg_ctx *c, const shg_shells *sh, const int32_t *pairs, int64_t n,
-                                const int64_t *out_off, const double *out, float *y)
+                                const int64_t *out_off, const double *out, const double *dout, float *y)
 {
     if (!c || !sh || n < 0) return SHG_EINVAL;
     if (n == 0) return 0;
+    if (!pairs || !out_off || !out || !y) return set_err(c, SHG_EINVAL, "shg_block_logmax: NULL pointer");
     hipLaunchKernelGGL(k_block_logmax, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, pairs, sh->l,
-                       out_off, out, y);
+                       out_off, out, dout, y);
     HIP_TRY(c, hipGetLastError());
     return 0;
 }
@@ -779,23 +858,55 @@ __global__ void k_keep(int64_t n, const float *logb, const float *pred, const in
 }
 
 namespace shg {
-// screening decisions for a plan: keep flags (device int32 [n]); returns 0 or error
-int screen_pairs(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs, int64_t n,
-                 int deriv, double tau, shg_mlp *mlp, int32_t *keep, float *work /* [n * 15] */)
+bool mlp_covers(const shg_mlp *m, int op, int deriv)
 {
-    float *feat = work, *logb = work + (size_t)n * NF, *pred = logb + n;
-    int32_t *inr = (int32_t *)(pred + n);
-    int rc = shg_screen_features(c, sh, op, omega, pairs, n, deriv, feat, logb);
-    if (rc) return rc;
-    // the model predicts value magnitudes of the operators it was trained on
-    if (deriv || (op != SHG_COULOMB && op != SHG_ERFC)) mlp = nullptr;
-    if (mlp) {
-        if (mlp->ctx != c) return set_err(c, SHG_EINVAL, "screen: model belongs to another context");
-        if ((rc = mlp_predict(mlp, feat, n, pred, inr))) return rc;
+    return m && op >= 0 && op < 5 && ((m->ops_mask >> op) & 1u) && (!deriv || m->deriv_targets);
+}
+
+// Screening stage of a plan, enqueued on `s` (graph-capturable: kernels only):
+// per-shell statistics from the folded weights w, then keep[i] for every
+// class-sorted position i of the n records. A pair is kept when the analytic
+// bound of any operator reaches tau, and, with a model in scope (one operator),
+// unless its prediction plus margin is below log10(tau) with every feature in
+// the training range. work: n * 15 floats when a model is used.
+int plan_screen_enqueue(shg_ctx *c, hipStream_t s, const shg_shells *sh, const double *w, double *stats,
+                        const PairRec *rec, int64_t n, int nops, const int *ops, const double *omegas, int deriv,
+                        double tau, shg_mlp *mlp, float *work, int32_t *keep)
+{
+    if (nops < 1 || nops > 5) return set_err(c, SHG_EINVAL, "screen: 1 to 5 operators");
+    if (mlp && (nops != 1 || !mlp_covers(mlp, ops[0], deriv))) mlp = nullptr;
+    if (mlp && mlp->ctx != c) return set_err(c, SHG_EINVAL, "screen: model belongs to another context");
+    static const BoundTab bt = build_bound_table();
+    PlanOps po{};
+    po.nops = nops;
+    for (int o = 0; o < nops; ++o) {
+        po.op[o] = ops[o];
+        po.omega[o] = omegas[o];
     }
-    hipLaunchKernelGGL(k_keep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, logb, pred, inr,
-                       (float)log10(tau), mlp ? mlp->margin : 0.0f, mlp ? 1 : 0, keep);
+    if (sh->nshell > 0)
+        hipLaunchKernelGGL(k_shell_stats, dim3((sh->nshell + 255) / 256), dim3(256), 0, s, sh->nshell, sh->nprim,
+                           sh->prim_off, sh->exps, w, stats);
+    if (n > 0) {
+        float *feat = mlp ? work : nullptr, *logb = mlp ? work + (size_t)n * NF : nullptr;
+        hipLaunchKernelGGL(k_plan_bound, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, rec, sh->center,
+                           sh->l, stats, po, deriv, mlp ? mlp->deriv_targets : deriv, bt, tau, keep, feat, logb);
+        if (mlp) {
+            float *pred = logb + n;
+            int32_t *inr = (int32_t *)(pred + n);
+            hipLaunchKernelGGL(k_mlp_pack, dim3((NH * 16 + 2 * NH * NH + 255) / 256), dim3(256), 0, s, mlp->p,
+                               mlp->wb);
+            const int64_t tiles = (n + 15) / 16;
+            const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 4096);
+            hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, s, n, feat, mlp->wb, mlp->p, mlp->norm, pred,
+                               inr);
+            hipLaunchKernelGGL(k_keep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, logb, pred, inr,
+                               (float)log10(tau), mlp->margin, 1, keep);
+        }
+    }
     HIP_TRY(c, hipGetLastError());
     return 0;
 }
+
+// bytes of per-shell statistics a plan's screening stage needs
+size_t plan_screen_stats_doubles(int nshell) { return (size_t)nshell * STAT + 1; }
 }  // namespace shg

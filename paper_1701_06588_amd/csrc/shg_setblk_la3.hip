@@ -1,0 +1,13 @@
+// k_setblk instantiations for l_a = 3 (every l_b, without and with derivatives)
+#include "shg_sets.h"
+namespace shg {
+const setblk_fn *setblk_table_la3()
+{
+    static const setblk_fn t[2 * (LMAX + 1)] = {
+        &launch_setblk<3, 0, false>, &launch_setblk<3, 0, true>, &launch_setblk<3, 1, false>,
+        &launch_setblk<3, 1, true>,  &launch_setblk<3, 2, false>, &launch_setblk<3, 2, true>,
+        &launch_setblk<3, 3, false>, &launch_setblk<3, 3, true>,  &launch_setblk<3, 4, false>,
+        &launch_setblk<3, 4, true>};
+    return t;
+}
+}  // namespace shg

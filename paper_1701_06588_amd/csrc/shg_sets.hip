@@ -1,0 +1,367 @@
+// shg_sets.hip -- family basis sets (Sec. III): shg_set_pairs.
+//
+// Per call:
+//   k_prep_set_funcs   validation; N_l and folded weights w = N_l c / (2 alpha)^l
+//                      of every contracted function (one wave per set)
+//   k_set_count        per set pair: validation, radial-scratch size, l-block
+//                      items counted per bin (la, lb, na, nb) in LDS
+//   scan               set-pair offsets into the radial scratch; bin starts
+//   k_set_scatter      item records in bin order (one global atomic per bin and
+//                      workgroup)
+//   k_set_radial       one wave per set pair: primitive radial terms for every
+//                      primitive pair, O^(k) = C_a^T G^(k) C_b through LDS
+//   k_setblk<la,lb,D>  per non-empty bin: the l-block elements (shg_sets.h)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "shg_ctx.h"
+#include "shg_sets.h"
+
+using namespace shg;
+
+namespace {
+
+constexpr int SET_NBIN = (LMAX + 1) * (LMAX + 1) * 81;   // (la, lb, na - 1, nb - 1), na, nb <= 9
+constexpr int SET_TPB = 256;
+
+__device__ __forceinline__ int set_bin(int la, int lb, int na, int nb)
+{
+    return ((la * (LMAX + 1) + lb) * 9 + na - 1) * 9 + nb - 1;
+}
+
+// validation of each set and the folded weights of its functions; one wave per set
+__global__ void k_prep_set_funcs(shg_sets s, double *w, int32_t *err)
+{
+    const int si = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (si >= s.nset) return;
+    const int K = s.nexp[si], nf = s.nfun[si];
+    const int64_t e0 = s.exp_off[si], f0 = s.fun_off[si];
+    if (K < 1 || K > SET_KMAX || e0 < 0 || e0 + K > s.nexp_total) {
+        if (lane == 0) atomicOr(err, ERR_SHELL_K);
+        return;
+    }
+    if (nf < 1 || nf > SET_FMAX || f0 < 0 || f0 + nf > s.nfun_total) {
+        if (lane == 0) atomicOr(err, ERR_SET_FUN);
+        return;
+    }
+    bool bad = false;
+    for (int k = 0; k < K; ++k) {
+        const double e = s.exps[e0 + k];
+        bad |= !(e > 0.0) || !(e < 1e300);
+    }
+    if (bad) {
+        if (lane == 0) atomicOr(err, ERR_SHELL_EXP);
+        return;
+    }
+    int lprev = 0;
+    for (int f = 0; f < nf; ++f) {
+        const int l = s.fun_l[f0 + f];
+        const int64_t co = s.coef_off[f0 + f];
+        if (l < lprev || l > LMAX || co < 0 || co + K > s.ncoef_total) {
+            if (lane == 0) atomicOr(err, l > LMAX || l < 0 ? ERR_SHELL_L : ERR_SET_FUN);
+            return;
+        }
+        lprev = l;
+    }
+    for (int f = 0; f < nf; ++f) {
+        const int l = s.fun_l[f0 + f];
+        const int64_t co = s.coef_off[f0 + f];
+        double t = 0.0;
+        if (lane < K * K) {
+            const int qa = lane / K, qb = lane - qa * K;
+            t = shell_norm_term(l, s.exps[e0 + qa], s.exps[e0 + qb], s.coefs[co + qa], s.coefs[co + qb]);
+        }
+        for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
+        if (lane < K) {
+            const double N = shell_norm_from_sum(l, t);
+            double a2 = 2.0 * s.exps[e0 + lane], p = 1.0;
+            for (int q = 0; q < l; ++q) p *= a2;
+            w[co + lane] = N * s.coefs[co + lane] / p;
+        }
+    }
+}
+
+// walks the l-block items of set pair (sa, sb) in a fixed order: A's functions
+// grouped by l, then B's, each group cut into chunks of at most the bin's
+// function counts; f(bin, item fields) per item
+template <class F>
+__device__ __forceinline__ void for_items(const shg_sets &s, int sa, int sb, int deriv, F &&f)
+{
+    const int64_t fa0 = s.fun_off[sa], fb0 = s.fun_off[sb];
+    const int nfa = s.nfun[sa], nfb = s.nfun[sb];
+    int row = 0;
+    for (int ia = 0; ia < nfa;) {
+        const int la = s.fun_l[fa0 + ia];
+        int ja = ia;
+        while (ja < nfa && s.fun_l[fa0 + ja] == la) ++ja;
+        const int na_tot = ja - ia;
+        int col = 0;
+        for (int ib = 0; ib < nfb;) {
+            const int lb = s.fun_l[fb0 + ib];
+            int jb = ib;
+            while (jb < nfb && s.fun_l[fb0 + jb] == lb) ++jb;
+            const int nb_tot = jb - ib;
+            const int fpm = set_fp_max(la, lb, deriv != 0);
+            const int nbc = min(nb_tot, fpm), nac = min(na_tot, max(1, fpm / nbc));
+            for (int a0 = 0; a0 < na_tot; a0 += nac)
+                for (int b0 = 0; b0 < nb_tot; b0 += nbc) {
+                    const int na = min(nac, na_tot - a0), nb = min(nbc, nb_tot - b0);
+                    f(set_bin(la, lb, na, nb), ia + a0, ib + b0, row + a0 * (2 * la + 1), col + b0 * (2 * lb + 1));
+                }
+            col += nb_tot * (2 * lb + 1);
+            ib = jb;
+        }
+        row += na_tot * (2 * la + 1);
+        ia = ja;
+    }
+}
+
+// per set pair: validation, radial-scratch size (nfa nfb SET_KS doubles) and
+// item counts per bin (LDS histogram, one global atomic per non-empty bin)
+__global__ __launch_bounds__(SET_TPB) void k_set_count(int64_t n, const int32_t *sp, shg_sets s, int deriv,
+                                                       int64_t *osz, int32_t *hist, int32_t *err)
+{
+    __shared__ int32_t lh[SET_NBIN];
+    for (int b = threadIdx.x; b < SET_NBIN; b += SET_TPB) lh[b] = 0;
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * SET_TPB + threadIdx.x;
+    if (p < n) {
+        const int sa = sp[2 * p], sb = sp[2 * p + 1];
+        if (sa < 0 || sa >= s.nset || sb < 0 || sb >= s.nset) {
+            atomicOr(err, ERR_PAIR_INDEX);
+            osz[p] = 0;
+        } else {
+            osz[p] = (int64_t)s.nfun[sa] * s.nfun[sb] * SET_KS;
+            for_items(s, sa, sb, deriv, [&](int bin, int, int, int, int) { atomicAdd(&lh[bin], 1); });
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < SET_NBIN; b += SET_TPB)
+        if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
+// item records in bin order: counts per bin in LDS, one range per bin and
+// workgroup reserved with a global atomic, then each item placed
+__global__ __launch_bounds__(SET_TPB) void k_set_scatter(int64_t n, const int32_t *sp, shg_sets s, int deriv,
+                                                         const int64_t *out_off, const int64_t *obase,
+                                                         const int64_t *nsgf, int32_t *cursor, SetItem *items)
+{
+    __shared__ int32_t cnt[SET_NBIN];
+    __shared__ int32_t gb[SET_NBIN];
+    for (int b = threadIdx.x; b < SET_NBIN; b += SET_TPB) cnt[b] = 0;
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * SET_TPB + threadIdx.x;
+    bool ok = false;
+    int sa = 0, sb = 0;
+    if (p < n) {
+        sa = sp[2 * p];
+        sb = sp[2 * p + 1];
+        ok = sa >= 0 && sa < s.nset && sb >= 0 && sb < s.nset;
+    }
+    if (ok) for_items(s, sa, sb, deriv, [&](int bin, int, int, int, int) { atomicAdd(&cnt[bin], 1); });
+    __syncthreads();
+    for (int b = threadIdx.x; b < SET_NBIN; b += SET_TPB) {
+        if (cnt[b]) gb[b] = atomicAdd(&cursor[b], cnt[b]);
+        cnt[b] = 0;
+    }
+    __syncthreads();
+    if (ok) {
+        const int ld = (int)nsgf[sb];
+        const int64_t blk = nsgf[sa] * nsgf[sb];
+        for_items(s, sa, sb, deriv, [&](int bin, int fa, int fb, int row0, int col0) {
+            const int32_t pos = gb[bin] + atomicAdd(&cnt[bin], 1);
+            items[pos] = SetItem{sa, sb, fa, fb, row0, col0, ld, s.nfun[sb], out_off[p], obase[p], blk, 0};
+        });
+    }
+}
+
+// spherical functions per set
+__global__ void k_set_nsgf(shg_sets s, int64_t *nsgf)
+{
+    const int si = blockIdx.x * blockDim.x + threadIdx.x;
+    if (si >= s.nset) return;
+    int64_t t = 0;
+    const int nf = min(max(s.nfun[si], 0), SET_FMAX);
+    for (int f = 0; f < nf; ++f) t += 2 * s.fun_l[s.fun_off[si] + f] + 1;
+    nsgf[si] = t;
+}
+
+// exclusive scan of n int64 values by one workgroup (sizes of the set pairs'
+// radial scratch); out[n] = total
+__global__ __launch_bounds__(256) void k_scan_i64(int64_t n, const int64_t *in, int64_t *out)
+{
+    __shared__ int64_t part[256];
+    const int t = threadIdx.x;
+    const int64_t per = (n + 255) / 256, lo = min(n, t * per), hi = min(n, lo + per);
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += in[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int64_t v = part[i];
+            part[i] = acc;
+            acc += v;
+        }
+        out[n] = acc;
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t v = in[i];
+        out[i] = acc;
+        acc += v;
+    }
+}
+
+// one wave per set pair: G^(k)[alpha][beta] of every primitive pair (a lane
+// each), T^(k)[alpha][fb] = sum_beta G^(k) w_b[fb][beta], then
+// O^(k)[fa][fb] = sum_alpha w_a[fa][alpha] T^(k)[alpha][fb] for the k of each
+// function pair (eq. O_rab2_deriv as C_a^T G C_b)
+constexpr int RAD_WAVES = 4;
+
+__global__ __launch_bounds__(64 * RAD_WAVES) void k_set_radial(int64_t n, const int32_t *sp, shg_sets s,
+                                                               const double *w, int op, double omega, int deriv,
+                                                               const double *tab, const int64_t *obase, double *O)
+{
+    __shared__ double sG[RAD_WAVES][SET_KS][64];
+    __shared__ double sTm[RAD_WAVES][SET_KS][SET_KMAX * SET_FMAX];
+    __shared__ double sWa[RAD_WAVES][SET_FMAX * SET_KMAX], sWb[RAD_WAVES][SET_FMAX * SET_KMAX];
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int64_t p = (int64_t)blockIdx.x * RAD_WAVES + wv;
+    const bool live = p < n;
+    int sa = 0, sb = 0, ka = 1, kb = 1, nfa = 1, nfb = 1, kmax = 0;
+    int64_t fa0 = 0, fb0 = 0, ea0 = 0, eb0 = 0;
+    if (live) {
+        sa = sp[2 * p];
+        sb = sp[2 * p + 1];
+        ka = s.nexp[sa];
+        kb = s.nexp[sb];
+        nfa = s.nfun[sa];
+        nfb = s.nfun[sb];
+        fa0 = s.fun_off[sa];
+        fb0 = s.fun_off[sb];
+        ea0 = s.exp_off[sa];
+        eb0 = s.exp_off[sb];
+        kmax = s.fun_l[fa0 + nfa - 1] + s.fun_l[fb0 + nfb - 1] + (deriv ? 1 : 0);   // functions sorted by l
+        const double X0 = s.center[3 * sa] - s.center[3 * sb], X1 = s.center[3 * sa + 1] - s.center[3 * sb + 1],
+                     X2 = s.center[3 * sa + 2] - s.center[3 * sb + 2];
+        const double R2 = fma(X0, X0, fma(X1, X1, X2 * X2));
+        if (lane < ka * kb) {
+            const int ia = lane / kb, ib = lane - ia * kb;
+            double g[SET_KS];
+            radial_rt<0, SET_KS - 1>(op, s.exps[ea0 + ia], s.exps[eb0 + ib], R2, omega, tab, g);
+#pragma unroll
+            for (int k = 0; k < SET_KS; ++k) sG[wv][k][lane] = g[k];
+        }
+        for (int e = lane; e < nfa * ka; e += 64) {
+            const int f = e / ka, q = e - f * ka;
+            sWa[wv][e] = w[s.coef_off[fa0 + f] + q];
+        }
+        for (int e = lane; e < nfb * kb; e += 64) {
+            const int f = e / kb, q = e - f * kb;
+            sWb[wv][e] = w[s.coef_off[fb0 + f] + q];
+        }
+    }
+    __syncthreads();
+    if (live) {
+        const int nt = (kmax + 1) * ka * nfb;
+        for (int e = lane; e < nt; e += 64) {
+            const int k = e / (ka * nfb), r = e - k * (ka * nfb);
+            const int ia = r / nfb, fb = r - ia * nfb;
+            double t = 0.0;
+            for (int ib = 0; ib < kb; ++ib) t = fma(sG[wv][k][ia * kb + ib], sWb[wv][fb * kb + ib], t);
+            sTm[wv][k][ia * nfb + fb] = t;
+        }
+    }
+    __syncthreads();
+    if (live) {
+        for (int e = lane; e < nfa * nfb; e += 64) {
+            const int fa = e / nfb, fb = e - fa * nfb;
+            const int la = s.fun_l[fa0 + fa], lb = s.fun_l[fb0 + fb];
+            const int klo = la > lb ? la : lb, khi = la + lb + (deriv ? 1 : 0);
+            double *dst = O + obase[p] + (int64_t)e * SET_KS;
+            for (int k = klo; k <= khi; ++k) {
+                double o = 0.0;
+                for (int ia = 0; ia < ka; ++ia) o = fma(sWa[wv][fa * ka + ia], sTm[wv][k][ia * nfb + fb], o);
+                dst[k] = o;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int shg_set_pairs(shg_ctx *c, const shg_sets *sets, shg_op op, double omega, const int32_t *set_pairs,
+                             int64_t n, const int64_t *out_off, double *out, double *dout)
+{
+    const char *what = "shg_set_pairs";
+    if (!c) return SHG_EINVAL;
+    if ((int)op < 0 || (int)op > 4) return set_err(c, SHG_EINVAL, "%s: unknown operator %d", what, (int)op);
+    if ((op == SHG_ERF || op == SHG_ERFC || op == SHG_GAUSS) && !(omega > 0.0 && omega < 1e300))
+        return set_err(c, SHG_EINVAL, "%s: omega must be positive and finite for this operator", what);
+    if (!sets) return set_err(c, SHG_EINVAL, "%s: set table is NULL", what);
+    if (sets->nset < 0 || sets->nexp_total < 0 || sets->nfun_total < 0 || sets->ncoef_total < 0 || n < 0)
+        return set_err(c, SHG_EINVAL, "%s: negative count", what);
+    if (n >= (int64_t)1 << 31) return set_err(c, SHG_EINVAL, "%s: n >= 2^31 set pairs per call", what);
+    if (n == 0) return 0;
+    if (sets->nset > 0 && (!sets->center || !sets->nexp || !sets->exp_off || !sets->exps || !sets->nfun ||
+                           !sets->fun_off || !sets->fun_l || !sets->coef_off || !sets->coefs))
+        return set_err(c, SHG_EINVAL, "%s: NULL array in the set table", what);
+    if (!set_pairs || !out_off || !out) return set_err(c, SHG_EINVAL, "%s: NULL pointer argument", what);
+    const int deriv = dout ? 1 : 0;
+    hipStream_t s = c->stream;
+    int rc = 0;
+    if ((rc = grow(c, c->set_w, c->set_w_cap, (size_t)sets->ncoef_total + 1))) return rc;
+    if ((rc = grow(c, c->set_osz, c->set_osz_cap, (size_t)n * 2 + 2))) return rc;
+    if ((rc = grow(c, c->set_nsgf, c->set_nsgf_cap, (size_t)sets->nset + 1))) return rc;
+    int64_t *osz = c->set_osz, *obase = c->set_osz + n + 1;
+    int32_t *hist = c->bins, *cursor = c->bins + (NBINS_MAX + 1);
+    static_assert(SET_NBIN <= NBINS_MAX, "set bins fit the histogram");
+    hipLaunchKernelGGL(k_fill_i32, dim3((SET_NBIN + 1 + 255) / 256), dim3(256), 0, s, hist, 0, SET_NBIN + 1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->err, 0, 1);
+    if (sets->nset > 0)
+        hipLaunchKernelGGL(k_prep_set_funcs, dim3((sets->nset + 3) / 4), dim3(256), 0, s, *sets, c->set_w, c->err);
+    // validation first: the item walk reads the function lists it checks
+    HIP_TRY(c, hipMemcpyAsync(c->host_rb, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if ((rc = decode_err(c, c->host_rb[0], what))) return rc;
+    if (sets->nset > 0)
+        hipLaunchKernelGGL(k_set_nsgf, dim3((sets->nset + 255) / 256), dim3(256), 0, s, *sets, c->set_nsgf);
+    const unsigned gb = (unsigned)((n + SET_TPB - 1) / SET_TPB);
+    hipLaunchKernelGGL(k_set_count, dim3(gb), dim3(SET_TPB), 0, s, n, set_pairs, *sets, deriv, osz, hist, c->err);
+    hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(256), 0, s, n, osz, obase);
+    hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(256), 0, s, hist, SET_NBIN, cursor, cursor);
+    HIP_TRY(c, hipMemcpyAsync(c->host_rb, cursor, (SET_NBIN + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(c->host_rb + SET_NBIN + 1, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int64_t o_total = 0;
+    HIP_TRY(c, hipMemcpyAsync(&o_total, obase + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if ((rc = decode_err(c, c->host_rb[SET_NBIN + 1], what))) return rc;
+    std::vector<int32_t> starts(c->host_rb, c->host_rb + SET_NBIN + 1);
+    const int64_t nitems = starts[SET_NBIN];
+    if ((rc = grow(c, c->set_items, c->set_items_cap, (size_t)nitems + 1))) return rc;
+    if ((rc = grow(c, c->set_O, c->set_O_cap, (size_t)o_total + 1))) return rc;
+    hipLaunchKernelGGL(k_set_scatter, dim3(gb), dim3(SET_TPB), 0, s, n, set_pairs, *sets, deriv, out_off, obase,
+                       c->set_nsgf, cursor, c->set_items);
+    hipLaunchKernelGGL(k_set_radial, dim3((unsigned)((n + RAD_WAVES - 1) / RAD_WAVES)), dim3(64 * RAD_WAVES), 0, s,
+                       n, set_pairs, *sets, c->set_w, (int)op, omega, deriv, c->boys, obase, c->set_O);
+    SetBlkArgs ba{c->set_items, sets->center, c->set_O, out, dout, 1, 1};
+    for (int la = 0; la <= LMAX; ++la)
+        for (int lb = 0; lb <= LMAX; ++lb)
+            for (int na = 1; na <= 9; ++na)
+                for (int nb = 1; nb <= 9; ++nb) {
+                    const int bin = ((la * (LMAX + 1) + lb) * 9 + na - 1) * 9 + nb - 1;
+                    const int64_t b0 = starts[bin], b1 = starts[bin + 1];
+                    if (b1 <= b0) continue;
+                    ba.na = na;
+                    ba.nb = nb;
+                    setblk_table(la)[lb * 2 + deriv](s, ba, b0, b1 - b0);
+                }
+    HIP_TRY(c, hipGetLastError());
+    return 0;
+}

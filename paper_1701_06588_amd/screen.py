@@ -1,10 +1,14 @@
 """Training of the learned prescreener on SHG block magnitudes.
 
-Data: for the Coulomb and erfc(0.11 r)/r operators, the 12 screening features
-of every shell pair (shg_screen_features) and the target log10 max|block|
+Data: for the five operators (overlap, Coulomb, erfc(0.11 r)/r, erf(0.33 r)/r,
+exp(-r^2)), the 12 screening features of every shell pair
+(shg_screen_features, derivative-aware bound) and the target log10 of the
+largest element of the value block and its three d/dR_a blocks
 (shg_block_logmax of blocks the engine evaluates) on the 500-atom workload and
 a subset of the molecules workload; split 80/20 by seed (pairs of held-out
-atoms / molecules). Training: Adam on the library's own kernels with the
+atoms / molecules). One model serves every operator (the operator code is a
+feature) and both value-only and value+derivative plans (its targets bound
+the values too). Training: Adam on the library's own kernels with the
 pinball loss at a high quantile (errs towards over-prediction). Calibration:
 the margin is the largest under-prediction on the held-out split (plus 0.25);
 the training range of every feature is stored so that out-of-range pairs fall
@@ -22,7 +26,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 MODEL = os.path.join(HERE, "prescreen_model.bin")
-OPS = ("coulomb", "erfc")
+OPS = ("overlap", "coulomb", "erfc", "erf", "gauss")
 
 
 def collect(engine, w, ops=OPS, max_pairs=None, seed=0):
@@ -41,11 +45,12 @@ def collect(engine, w, ops=OPS, max_pairs=None, seed=0):
     pairs = torch.as_tensor(np.ascontiguousarray(pairs_np, np.int32), device=dev)
     oo = torch.as_tensor(off, device=dev)
     out = torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
+    dout = torch.empty(max(3 * tot, 1), dtype=torch.float64, device=dev)
     Xs, ys = [], []
     for op in ops:
-        engine.pairs(dsh, op, w.omega[op], pairs, oo, out)
-        X, _ = shg.screen_features(engine, dsh, op, w.omega[op], pairs)
-        y = shg.block_logmax(engine, dsh, pairs, oo, out)
+        engine.pairs(dsh, op, w.omega[op], pairs, oo, out, dout)
+        X, _ = shg.screen_features(engine, dsh, op, w.omega[op], pairs, deriv=True)
+        y = shg.block_logmax(engine, dsh, pairs, oo, out, dout)
         Xs.append(X.clone())
         ys.append(y.clone())
     # held-out split: pairs whose first atom (or molecule) falls in a fixed 20%
@@ -55,7 +60,7 @@ def collect(engine, w, ops=OPS, max_pairs=None, seed=0):
     return torch.cat(Xs), torch.cat(ys), held
 
 
-def train(engine, X, y, held, epochs=40, batch=8192, lr=2e-3, quantile=0.999, seed=0, log=print):
+def train(engine, X, y, held, epochs=25, batch=8192, lr=2e-3, quantile=0.999, seed=0, log=print):
     import torch
     from paper_1701_06588_amd import shg
     Xtr, ytr = X[~held], y[~held]
@@ -67,6 +72,7 @@ def train(engine, X, y, held, epochs=40, batch=8192, lr=2e-3, quantile=0.999, se
     hi = Xtr.max(0).values.cpu().numpy()
     mlp = shg.Mlp(engine, seed)
     mlp.set_norm(mean, std, lo, hi)
+    mlp.set_scope(OPS, True)
     n = Xtr.shape[0]
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)

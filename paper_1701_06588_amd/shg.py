@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -20,9 +21,9 @@ EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pair
            "shg_set_tile_shape", "shg_get_tile_shape", "shg_autotune", "shg_tuning_save", "shg_tuning_load",
            "shg_profile_enable", "shg_profile_read", "shg_plan_create", "shg_plan_execute",
            "shg_plan_autotune", "shg_plan_set_mode", "shg_plan_mode", "shg_plan_destroy",
-           "shg_plan_stats", "shg_plan_kernel_ms", "shg_plan_skipped", "shg_plan_create_multi", "shg_plan_tile_order",
+           "shg_plan_stats", "shg_plan_kernel_ms", "shg_plan_skipped", "shg_plan_tile_order", "shg_set_aab_chunk", "shg_plan_time_kernels", "shg_plan_kernel_time", "shg_plan_set_tile_order", "shg_set_pairs",
            "shg_plan_create_screened", "shg_mlp_create", "shg_mlp_destroy", "shg_mlp_params", "shg_mlp_set_norm",
-           "shg_mlp_set_margin", "shg_mlp_train_step", "shg_mlp_grad", "shg_mlp_predict", "shg_mlp_save",
+           "shg_mlp_set_margin", "shg_mlp_set_scope", "shg_mlp_train_step", "shg_mlp_grad", "shg_mlp_predict", "shg_mlp_save",
            "shg_mlp_load", "shg_screen_features", "shg_block_logmax")
 
 
@@ -30,6 +31,13 @@ class ShgShells(C.Structure):
     _fields_ = [("nshell", C.c_int32), ("nprim_total", C.c_int64), ("center", C.c_void_p),
                 ("l", C.c_void_p), ("nprim", C.c_void_p), ("prim_off", C.c_void_p),
                 ("exps", C.c_void_p), ("coefs", C.c_void_p)]
+
+
+class ShgSets(C.Structure):
+    _fields_ = [("nset", C.c_int32), ("nexp_total", C.c_int64), ("nfun_total", C.c_int64),
+                ("ncoef_total", C.c_int64), ("center", C.c_void_p), ("nexp", C.c_void_p), ("exp_off", C.c_void_p),
+                ("exps", C.c_void_p), ("nfun", C.c_void_p), ("fun_off", C.c_void_p), ("fun_l", C.c_void_p),
+                ("coef_off", C.c_void_p), ("coefs", C.c_void_p)]
 
 
 class ShgError(RuntimeError):
@@ -62,6 +70,10 @@ def load_library(path: str = LIB_PATH):
     lib.shg_pairs_deriv.restype = C.c_int
     lib.shg_aab.argtypes = [P, C.POINTER(ShgShells), C.POINTER(ShgShells), P, C.c_int64, P, P, P]
     lib.shg_aab.restype = C.c_int
+    lib.shg_set_pairs.argtypes = [P, C.POINTER(ShgSets), C.c_int, C.c_double, P, C.c_int64, P, P, P]
+    lib.shg_set_pairs.restype = C.c_int
+    lib.shg_set_aab_chunk.argtypes = [P, C.c_int64]
+    lib.shg_set_aab_chunk.restype = C.c_int
     lib.shg_pairs_r2n.argtypes = [P, C.POINTER(ShgShells), C.c_int, P, C.c_int64, P, P, P]
     lib.shg_pairs_r2n.restype = C.c_int
     lib.shg_pairs_swap.argtypes = [P, C.POINTER(ShgShells), P, C.c_int64, P, P, P, P]
@@ -89,12 +101,13 @@ def load_library(path: str = LIB_PATH):
     lib.shg_plan_set_mode.argtypes = [P, I]
     lib.shg_plan_mode.argtypes = [P]
     lib.shg_plan_tile_order.argtypes = [P]
+    lib.shg_plan_set_tile_order.argtypes = [P, I]
     lib.shg_plan_destroy.argtypes = [P]
     lib.shg_plan_destroy.restype = None
     lib.shg_plan_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.shg_plan_kernel_ms.argtypes = [P, I, C.POINTER(C.c_double)]
-    lib.shg_plan_create_multi.argtypes = [P, C.POINTER(ShgShells), I, P, P, P, C.c_int64, P, P, P, C.c_double,
-                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]
+    lib.shg_plan_time_kernels.argtypes = [P, I]
+    lib.shg_plan_kernel_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.shg_plan_skipped.argtypes = [P, P, C.c_int64]
     lib.shg_plan_skipped.restype = C.c_int64
     lib.shg_plan_create_screened.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, P, P, P,
@@ -106,13 +119,14 @@ def load_library(path: str = LIB_PATH):
     lib.shg_mlp_params.argtypes = [P, P, P]
     lib.shg_mlp_set_norm.argtypes = [P, P, P, P, P]
     lib.shg_mlp_set_margin.argtypes = [P, C.c_float]
+    lib.shg_mlp_set_scope.argtypes = [P, C.c_uint32, I]
     lib.shg_mlp_train_step.argtypes = [P, P, P, I, C.c_float, C.c_float, P]
     lib.shg_mlp_grad.argtypes = [P, P, P, I, C.c_float, P, P]
     lib.shg_mlp_predict.argtypes = [P, P, C.c_int64, P, P]
     lib.shg_mlp_save.argtypes = [P, C.c_char_p]
     lib.shg_mlp_load.argtypes = [P, C.c_char_p]
     lib.shg_screen_features.argtypes = [P, C.POINTER(ShgShells), I, C.c_double, P, C.c_int64, I, P, P]
-    lib.shg_block_logmax.argtypes = [P, C.POINTER(ShgShells), P, C.c_int64, P, P, P]
+    lib.shg_block_logmax.argtypes = [P, C.POINTER(ShgShells), P, C.c_int64, P, P, P, P]
     _lib = lib
     return lib
 
@@ -137,6 +151,27 @@ class DeviceShells:
                            _ptr(self.prim_off), _ptr(self.exps), _ptr(self.coefs))
 
 
+class DeviceSets:
+    """A family-set table resident in device memory plus its C view."""
+
+    def __init__(self, st, device):
+        import torch
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a, dt), device=device)
+        self.center = t(st.center, np.float64)
+        self.nexp = t(st.nexp, np.int32)
+        self.exp_off = t(st.exp_off, np.int64)
+        self.exps = t(st.exps, np.float64)
+        self.nfun = t(st.nfun, np.int32)
+        self.fun_off = t(st.fun_off, np.int64)
+        self.fun_l = t(st.fun_l, np.int32)
+        self.coef_off = t(st.coef_off, np.int64)
+        self.coefs = t(st.coefs, np.float64)
+        self.host = st
+        self.c = ShgSets(int(st.n), int(len(st.exps)), int(len(st.fun_l)), int(len(st.coefs)), _ptr(self.center),
+                         _ptr(self.nexp), _ptr(self.exp_off), _ptr(self.exps), _ptr(self.nfun), _ptr(self.fun_off),
+                         _ptr(self.fun_l), _ptr(self.coef_off), _ptr(self.coefs))
+
+
 class Engine:
     """One shg_ctx bound to the current device and a torch stream."""
 
@@ -152,9 +187,16 @@ class Engine:
         if rc != 0:
             raise ShgError(rc, self.lib.shg_last_error(None).decode())
         self.ctx = h
+        # plans and models made on this context; closed before the context is
+        self._children = weakref.WeakSet()
+
+    def _adopt(self, obj):
+        self._children.add(obj)
 
     def close(self):
         if getattr(self, "ctx", None):
+            for ch in list(getattr(self, "_children", ())):
+                ch.close()
             self.lib.shg_destroy(self.ctx)
             self.ctx = None
 
@@ -214,6 +256,15 @@ class Engine:
                                           _ptr(out_off), _ptr(out), _ptr(dout))
         self._check(rc)
 
+    def sets(self, st) -> DeviceSets:
+        return DeviceSets(st, self.torch.device("cuda", self.torch.cuda.current_device()))
+
+    def set_pairs(self, dst: DeviceSets, op: str, omega: float, set_pairs, out_off, out, dout=None):
+        """shg_set_pairs: family-set pair blocks (and d/dR_A with `dout`) on device tensors."""
+        n = int(set_pairs.shape[0])
+        self._check(self.lib.shg_set_pairs(self.ctx, C.byref(dst.c), OPS[op], float(omega), _ptr(set_pairs), n,
+                                           _ptr(out_off), _ptr(out), _ptr(dout)))
+
     def pairs_r2n(self, dsh: DeviceShells, nr: int, pairs, out_off, out, dout=None):
         """shg_pairs_r2n: (a|r_a^{2n}|b) (and d/dR_a with `dout`) on device tensors."""
         n = int(pairs.shape[0])
@@ -234,6 +285,10 @@ class Engine:
         fl = C.c_double()
         self._check(self.lib.shg_fp64_ceiling(self.ctx, int(iters), int(blocks), _ptr(out), C.byref(fl)))
         return fl.value
+
+    def set_aab_chunk(self, chunk: int):
+        """shg_set_aab_chunk: triples per (class, chunk) work item of shg_aab"""
+        self._check(self.lib.shg_set_aab_chunk(self.ctx, int(chunk)))
 
     def aab(self, orb: DeviceShells, aux: DeviceShells, triples, out_off, out, dout=None):
         n = int(triples.shape[0])
@@ -274,6 +329,7 @@ class Plan:
                 C.byref(ns)))
             self.n_skipped = ns.value
         self.h = h
+        engine._adopt(self)
 
     def execute(self):
         self.engine._check(self.engine.lib.shg_plan_execute(self.h))
@@ -304,6 +360,21 @@ class Plan:
         self.engine._check(self.engine.lib.shg_plan_kernel_ms(self.h, reps, C.byref(ms)))
         return ms.value
 
+    def time_kernels(self, on: bool = True):
+        """record HIP events around the evaluation kernels of every later execute"""
+        self.engine._check(self.engine.lib.shg_plan_time_kernels(self.h, int(on)))
+
+    def kernel_time(self):
+        """(summed kernel ms, timed executions) since the last call; synchronises"""
+        ms, k = C.c_double(), C.c_int64()
+        self.engine._check(self.engine.lib.shg_plan_kernel_time(self.h, C.byref(ms), C.byref(k)))
+        return ms.value, k.value
+
+    def set_tile_order(self, order: str):
+        """fix the persistent queue's tile order without timing the alternatives"""
+        code = {"heaviest-first": 0, "alternating": 1, "round-robin": 2}[order]
+        self.engine._check(self.engine.lib.shg_plan_set_tile_order(self.h, code))
+
     @property
     def tile_order(self) -> str:
         return {0: "heaviest-first", 1: "alternating", 2: "round-robin"}.get(
@@ -311,7 +382,7 @@ class Plan:
 
     @property
     def mode(self) -> str:
-        return {0: "per-class", 1: "persistent", 2: "multi"}.get(self.engine.lib.shg_plan_mode(self.h), "?")
+        return {0: "per-class", 1: "persistent"}.get(self.engine.lib.shg_plan_mode(self.h), "?")
 
     def close(self):
         if getattr(self, "h", None):
@@ -323,31 +394,6 @@ class Plan:
             self.close()
         except Exception:
             pass
-
-
-class MultiPlan(Plan):
-    """Several operators on one pair list, one persistent kernel per execution
-    (shg_plan_create_multi); `outs` / `douts` are lists of device tensors, one
-    per operator; tau > 0 screens with the analytic bound (a pair is skipped only
-    when every operator's bound is below tau)."""
-
-    def __init__(self, engine: "Engine", dsh: DeviceShells, ops, omegas, pairs, out_off, outs, douts=None,
-                 tau: float = 0.0):
-        self.engine = engine
-        self.keep = (dsh, pairs, out_off, list(outs), list(douts) if douts is not None else None)
-        nops = len(ops)
-        op_arr = (C.c_int * nops)(*[OPS[o] for o in ops])
-        om_arr = (C.c_double * nops)(*[float(x) for x in omegas])
-        out_arr = (C.c_void_p * nops)(*[o.data_ptr() for o in outs])
-        dout_arr = (C.c_void_p * nops)(*[d.data_ptr() for d in douts]) if douts is not None else None
-        h = C.c_void_p()
-        ns = C.c_int64()
-        engine._check(engine.lib.shg_plan_create_multi(
-            engine.ctx, C.byref(dsh.c), nops, C.cast(op_arr, C.c_void_p), C.cast(om_arr, C.c_void_p), _ptr(pairs),
-            int(pairs.shape[0]), _ptr(out_off), C.cast(out_arr, C.c_void_p),
-            C.cast(dout_arr, C.c_void_p) if dout_arr is not None else None, float(tau), C.byref(h), C.byref(ns)))
-        self.n_skipped = ns.value
-        self.h = h
 
 
 NPARAM = 9217
@@ -362,6 +408,7 @@ class Mlp:
         h = C.c_void_p()
         engine._check(engine.lib.shg_mlp_create(engine.ctx, C.c_uint64(seed), C.byref(h)))
         self.h = h
+        engine._adopt(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -390,6 +437,13 @@ class Mlp:
 
     def set_margin(self, m: float):
         self.engine._check(self.engine.lib.shg_mlp_set_margin(self.h, float(m)))
+
+    def set_scope(self, ops, deriv_targets: bool):
+        """operators (names) the model predicts, and whether its targets include d/dR_a"""
+        mask = 0
+        for o in ops:
+            mask |= 1 << OPS[o]
+        self.engine._check(self.engine.lib.shg_mlp_set_scope(self.h, mask, int(deriv_targets)))
 
     def train_step(self, X, y, lr, quantile, loss_out=None):
         self.engine._check(self.engine.lib.shg_mlp_train_step(self.h, _ptr(X), _ptr(y), int(X.shape[0]), float(lr),
@@ -422,12 +476,13 @@ def screen_features(engine: Engine, dsh: DeviceShells, op: str, omega: float, pa
     return feat[:n], logb[:n]
 
 
-def block_logmax(engine: Engine, dsh: DeviceShells, pairs, out_off, out):
+def block_logmax(engine: Engine, dsh: DeviceShells, pairs, out_off, out, dout=None):
+    """log10 max|element| per block (values, and with `dout` the d/dR_a blocks too)"""
     torch = engine.torch
     n = int(pairs.shape[0])
     y = torch.empty(max(n, 1), dtype=torch.float32, device=pairs.device)
     engine._check(engine.lib.shg_block_logmax(engine.ctx, C.byref(dsh.c), _ptr(pairs), n, _ptr(out_off), _ptr(out),
-                                              _ptr(y)))
+                                              _ptr(dout), _ptr(y)))
     return y[:n]
 
 

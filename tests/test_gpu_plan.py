@@ -101,90 +101,3 @@ def test_plan_autotune_selects_a_mode(engine):
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
     plan.close()
-
-
-def _assert_close_blockwise(got, ref, starts, sizes, what):
-    """|got - ref| <= 64 eps max|ref block| per element: the fused kernel forms the
-    same sums as the single-operator path, but the compiler may contract a
-    multiply-add into an FMA in one kernel and not in the other."""
-    bmax = np.maximum.reduceat(np.abs(ref), starts)
-    scale = np.repeat(bmax, sizes)
-    err = np.abs(got - ref)
-    assert np.all(err <= 64 * np.finfo(np.float64).eps * scale), (what, float((err / np.maximum(scale, 1e-300)).max()))
-
-
-@pytest.mark.parametrize("deriv", [False, True])
-@pytest.mark.parametrize("ops", [("overlap", "coulomb", "erfc", "erf", "gauss"), ("erfc", "coulomb")])
-def test_multi_plan_matches_single_operator_path(engine, deriv, ops):
-    """One kernel for several operators gives each operator's blocks of the
-    single-operator path (values bitwise where both kernels round alike; every
-    element within 64 eps of its block's largest element)."""
-    import torch
-    from paper_1701_06588_amd import shg
-    w = inputs.small_pairs(79, 4000)
-    print(f"case multi plan small4000 ops={ops} deriv={deriv}", flush=True)
-    dsh, pairs, oo, out, dout = _setup(engine, w, deriv)
-    refs = []
-    for op in ops:
-        engine.pairs(dsh, op, w.omega[op], pairs, oo, out, dout)
-        torch.cuda.synchronize()
-        refs.append((out.clone(), dout.clone() if deriv else None))
-    outs = [torch.full_like(out, float("nan")) for _ in ops]
-    douts = [torch.full_like(dout, float("nan")) for _ in ops] if deriv else None
-    plan = shg.MultiPlan(engine, dsh, ops, [w.omega[o] for o in ops], pairs, oo, outs, douts)
-    assert plan.mode == "multi" and plan.n_skipped == 0
-    for rep in range(2):
-        for k in range(len(ops)):
-            outs[k].fill_(float("nan"))
-            if deriv:
-                douts[k].fill_(float("nan"))
-        plan.execute()
-        torch.cuda.synchronize()
-        off, tot = w.out_offsets()
-        sz = np.asarray(w.block_sizes(), np.int64)
-        for k, op in enumerate(ops):
-            _assert_close_blockwise(outs[k].cpu().numpy(), refs[k][0].cpu().numpy(), off, sz, (op, rep))
-            if deriv:
-                _assert_close_blockwise(douts[k].cpu().numpy(), refs[k][1].cpu().numpy(), 3 * off, 3 * sz,
-                                        (op, rep, "deriv"))
-    kept, nbytes = plan.stats()
-    assert kept == len(w.pairs)
-    plan.close()
-
-
-def test_multi_plan_screened(engine):
-    import torch
-    from paper_1701_06588_amd import shg
-    w = inputs.screen5000(n_atoms=700, box=24.0)
-    ops = ("overlap", "gauss", "coulomb")
-    print(f"case multi plan screened n={len(w.pairs)}", flush=True)
-    dsh, pairs, oo, out, dout = _setup(engine, w, True)
-    refs = []
-    for op in ops:
-        engine.pairs(dsh, op, w.omega[op], pairs, oo, out, dout)
-        torch.cuda.synchronize()
-        refs.append((out.cpu().numpy(), dout.cpu().numpy()))
-    outs = [torch.full_like(out, float("nan")) for _ in ops]
-    douts = [torch.full_like(dout, float("nan")) for _ in ops]
-    tau = 1e-12
-    plan = shg.MultiPlan(engine, dsh, ops, [w.omega[o] for o in ops], pairs, oo, outs, douts, tau=tau)
-    plan.execute()
-    torch.cuda.synchronize()
-    skipped = np.zeros(len(w.pairs), bool)
-    skipped[plan.skipped()] = True
-    assert skipped.sum() == plan.n_skipped > 0
-    off, tot = w.out_offsets()
-    sz = np.asarray(w.block_sizes(), np.int64)
-    es, ds = np.repeat(skipped, sz), np.repeat(skipped, 3 * sz)
-    for k, op in enumerate(ops):
-        g, dg = outs[k].cpu().numpy(), douts[k].cpu().numpy()
-        r, dr = refs[k]
-        gz, dgz = g.copy(), dg.copy()
-        gz[es] = r[es]
-        dgz[ds] = dr[ds]
-        _assert_close_blockwise(gz, r, off, sz, op)
-        _assert_close_blockwise(dgz, dr, 3 * off, 3 * sz, (op, "deriv"))
-        assert np.all(g[es] == 0) and np.all(dg[ds] == 0), op
-        # skipped only when every operator's bound is below tau, so every skipped element is tiny
-        assert np.all(np.abs(r[es]) <= tau) and np.all(np.abs(dr[ds]) <= tau), op
-    plan.close()

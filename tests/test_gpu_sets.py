@@ -1,0 +1,160 @@
+"""Family basis sets (shg_set_pairs) on the paper's MOLOPT data (Tables S2-S5)
+against the long-double oracle, five operators, values and d/dR_A; agreement
+with the shell path (each contracted function as a shell of its own)."""
+import numpy as np
+import pytest
+
+import oracle
+from parity import assert_parity
+from paper_1701_06588_amd import basis_molopt as bm
+from paper_1701_06588_amd import inputs
+
+pytestmark = pytest.mark.gpu
+OPS = ("overlap", "coulomb", "erfc", "erf", "gauss")
+
+
+@pytest.fixture(scope="module")
+def engine():
+    from paper_1701_06588_amd import shg
+    e = shg.Engine()
+    yield e
+    e.close()
+
+
+def random_system(seed, n_atoms, box, names, cutoff, same_center=True):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, box, size=(n_atoms, 3))
+    kinds = [names[i] for i in rng.integers(0, len(names), n_atoms)]
+    st = bm.make_sets(pos, kinds)
+    ap = inputs.atom_pairs_within(pos, cutoff, ordered=True, include_self=same_center)
+    return st, np.ascontiguousarray(ap, np.int32)
+
+
+def run_sets(engine, st, sp, op, omega, deriv):
+    import torch
+    dev = torch.device("cuda")
+    ds = engine.sets(st)
+    nsgf = st.nsgf()
+    sz = nsgf[sp[:, 0]] * nsgf[sp[:, 1]]
+    off = np.zeros(len(sz), np.int64)
+    off[1:] = np.cumsum(sz[:-1])
+    tot = int(sz.sum())
+    out = torch.full((max(tot, 1),), float("nan"), dtype=torch.float64, device=dev)
+    dout = torch.full((max(3 * tot, 1),), float("nan"), dtype=torch.float64, device=dev) if deriv else None
+    engine.set_pairs(ds, op, omega, torch.as_tensor(sp, device=dev), torch.as_tensor(off, device=dev), out, dout)
+    torch.cuda.synchronize()
+    return off, sz, out.cpu().numpy()[:tot], (dout.cpu().numpy()[:3 * tot] if deriv else None)
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_set_pairs_molopt_vs_oracle(engine, op):
+    """H-DZVP, O-DZVP, O-TZV2PX and Cu-DZVP sets at random positions (same-center
+    pairs included): every element of every block against the oracle."""
+    st, sp = random_system(101, 40, 9.0, list(bm.ORBITAL), 7.0)
+    print(f"case sets molopt op={op} set_pairs={len(sp)}", flush=True)
+    w = inputs.OMEGA[op]
+    off, sz, out, dout = run_sets(engine, st, sp, op, w, True)
+    ro, rd = oracle.set_pairs(st, op, w, sp, off, deriv=True, long_double=True)
+    assert_parity(out, ro, off, sz, False, f"sets {op}")
+    assert_parity(dout, rd, off, sz, True, f"sets {op} deriv")
+
+
+def test_set_pairs_values_only_and_shell_path(engine):
+    """values-only calls give the value blocks of the derivative call, and each
+    set block equals the blocks of the shell path (the functions as shells)"""
+    import torch
+    st, sp = random_system(102, 60, 12.0, ["O-DZVP", "H-DZVP", "Cu-DZVP"], 8.0)
+    print(f"case sets vs shells set_pairs={len(sp)}", flush=True)
+    off, sz, out, _ = run_sets(engine, st, sp, "coulomb", 0.0, False)
+    _, _, out_d, dout_d = run_sets(engine, st, sp, "coulomb", 0.0, True)
+    # the two instantiations may contract a multiply-add differently: equal to a few ulp of each block
+    bmax = np.repeat(np.maximum.reduceat(np.abs(out_d), off), sz)
+    assert np.all(np.abs(out - out_d) <= 8 * np.finfo(np.float64).eps * np.maximum(bmax, 1e-300))
+    sh, first = st.as_shells()
+    fl = sh.l
+    pairs, where = [], []
+    for i, (a, b) in enumerate(sp):
+        ra = 0
+        for fa in range(first[a], first[a] + st.nfun[a]):
+            cb = 0
+            for fb in range(first[b], first[b] + st.nfun[b]):
+                pairs.append((fa, fb))
+                where.append((i, ra, cb, 2 * fl[fa] + 1, 2 * fl[fb] + 1))
+                cb += 2 * fl[fb] + 1
+            ra += 2 * fl[fa] + 1
+    pairs = np.asarray(pairs, np.int32)
+    fsz = np.array([x[3] * x[4] for x in where], np.int64)
+    foff = np.zeros(len(fsz), np.int64)
+    foff[1:] = np.cumsum(fsz[:-1])
+    dev = torch.device("cuda")
+    r = torch.empty(int(fsz.sum()), dtype=torch.float64, device=dev)
+    engine.pairs(engine.shells(sh), "coulomb", 0.0, torch.as_tensor(pairs, device=dev),
+                 torch.as_tensor(foff, device=dev), r)
+    r = r.cpu().numpy()
+    nsgf = st.nsgf()
+    worst = 0.0
+    for k, (i, ra, cb, na, nb) in enumerate(where):
+        blk = out[off[i]:off[i] + sz[i]].reshape(nsgf[sp[i, 0]], nsgf[sp[i, 1]])[ra:ra + na, cb:cb + nb]
+        ref = r[foff[k]:foff[k] + na * nb].reshape(na, nb)
+        scale = max(1.0, np.abs(ref).max())
+        worst = max(worst, float((np.abs(blk - ref) / (1e-13 * np.abs(ref) + 1e-15 * scale)).max()))
+    assert worst <= 1.0, worst
+
+
+def test_set_pairs_errors(engine):
+    import torch
+    from paper_1701_06588_amd import shg
+    st, sp = random_system(103, 4, 5.0, ["O-DZVP"], 10.0)
+    dev = torch.device("cuda")
+    nsgf = st.nsgf()
+    off = torch.zeros(len(sp), dtype=torch.int64, device=dev)
+    out = torch.zeros(int((nsgf[sp[:, 0]] * nsgf[sp[:, 1]]).sum()), dtype=torch.float64, device=dev)
+    bad = sp.copy()
+    bad[0, 1] = 99
+    with pytest.raises(shg.ShgError):
+        engine.set_pairs(engine.sets(st), "overlap", 0.0, torch.as_tensor(bad, device=dev), off, out)
+    st2, _ = random_system(103, 4, 5.0, ["O-DZVP"], 10.0)
+    st2.fun_l[2], st2.fun_l[4] = 2, 1          # functions not grouped by non-decreasing l
+    with pytest.raises(shg.ShgError):
+        engine.set_pairs(engine.sets(st2), "overlap", 0.0, torch.as_tensor(sp, device=dev), off, out)
+    engine.set_pairs(engine.sets(st), "overlap", 0.0, torch.as_tensor(sp[:0], device=dev), off[:0], out)
+
+
+def test_aab_lri_molopt_vs_oracle(engine):
+    """the three-index overlap on the paper's data: MOLOPT orbital functions (as
+    shells) and LRI-MOLOPT auxiliary functions (Tables S6-S8) of H, O and Cu"""
+    import torch
+    rng = np.random.default_rng(104)
+    names = ["H", "O", "Cu"]
+    pos = rng.uniform(0.0, 6.0, size=(6, 3))
+    kinds = [names[i % 3] for i in range(6)]
+    orb_names = {"H": "H-DZVP", "O": "O-DZVP", "Cu": "Cu-DZVP"}
+    st = bm.make_sets(pos, [orb_names[k] for k in kinds])
+    orb, first = st.as_shells()
+    keep = orb.l <= 3
+    aux = bm.aux_shells(pos, [k + "-LRI" for k in kinds])
+    tri = []
+    for x in range(6):
+        for y in range(6):
+            fa = [f for f in range(first[x], first[x] + st.nfun[x])]
+            fb = [f for f in range(first[y], first[y] + st.nfun[y])]
+            ta = np.nonzero(aux.atom == x)[0]
+            for a in fa:
+                for t in ta[::3]:
+                    for b in fb[::2]:
+                        tri.append((a, t, b))
+    tri = np.asarray(tri, np.int32)
+    assert keep.all()
+    w = inputs.Workload("lri", orb, np.zeros((0, 2), np.int32), ("aab",), {}, True, aux=aux, triples=tri)
+    print(f"case aab lri/molopt triples={len(tri)}", flush=True)
+    off, tot = w.out_offsets()
+    sz = w.block_sizes()
+    dev = torch.device("cuda")
+    out = torch.full((tot,), float("nan"), dtype=torch.float64, device=dev)
+    dout = torch.full((3 * tot,), float("nan"), dtype=torch.float64, device=dev)
+    engine.aab(engine.shells(orb), engine.shells(aux), torch.as_tensor(tri, device=dev),
+               torch.as_tensor(off, device=dev), out, dout)
+    torch.cuda.synchronize()
+    ro, rd = oracle.aab(orb, aux, tri, off, deriv=True, long_double=True)
+    assert_parity(out.cpu().numpy(), ro, off, sz, False, "aab lri")
+    assert_parity(dout.cpu().numpy(), rd, off, sz, True, "aab lri deriv")
