@@ -101,6 +101,26 @@ int shg_pairs_deriv(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
                     const int32_t *pairs, int64_t n, const int64_t *out_off,
                     double *out, double *dout);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Computes
+ * exactly what shg_pairs (dout NULL) or shg_pairs_deriv (dout non-NULL)
+ * computes, with the same kernels, but keeps the binning scratch (folded
+ * weights, class keys, sorted ids, pair records) in a fixed device array of
+ * the library instead of context memory grown on demand; the call performs no
+ * device or host allocation. The array is 32 MiB, one copy per GPU the library
+ * runs on, held until the process ends. Limits: n <= SHG_NOALLOC_MAX_PAIRS
+ * (n = 0 is a no-op success) and sh->nprim_total <= SHG_NOALLOC_MAX_PRIMS, else
+ * SHG_EINVAL; op SHG_OVERLAP..SHG_GAUSS (SHG_GCOULOMB: SHG_EINVAL). Every
+ * call on one GPU shares that GPU's array (across contexts too), so calls
+ * that overlap in time on one GPU race; serialise them (one stream, or the
+ * call's own synchronisation: like shg_pairs it synchronises the context
+ * stream once, after binning). Other arguments and errors as in shg_pairs. */
+#define SHG_NOALLOC_MAX_PAIRS (1 << 20)
+#define SHG_NOALLOC_MAX_PRIMS (1 << 20)
+int shg_pairs_noalloc(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
+                      const int32_t *pairs, int64_t n, const int64_t *out_off,
+                      double *out, double *dout);
+
 /* (a|r_a^{2n}|b) (Sec. II.C, eq. ara2nb_def, evaluated by eqs. ara2nb and
  * T_rab2_deriv): the local operator r_a^{2n} = |r - R_a|^{2n} centred on a's
  * center, 0 <= nr <= 5 (else SHG_EINVAL; nr = 0 is the overlap).

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "../../include/shg.h"
@@ -158,6 +159,43 @@ __global__ __launch_bounds__(BIN_TPB) void k_scatter(int64_t n, const int32_t *k
 }  // namespace shg
 
 // ---------------------------------------------------------------------------
+// fixed scratch of shg_pairs_noalloc: one array per device, held until the
+// process ends; host code uses the address hipGetSymbolAddress gives for the
+// current device (never the array's name, which on the host is only a stand-in)
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t NOALLOC_W_BYTES = (size_t)SHG_NOALLOC_MAX_PRIMS * sizeof(double);
+constexpr size_t NOALLOC_KEYS_BYTES = (size_t)SHG_NOALLOC_MAX_PAIRS * sizeof(int32_t);
+constexpr size_t NOALLOC_REC_BYTES = (size_t)SHG_NOALLOC_MAX_PAIRS * sizeof(PairRec);
+constexpr size_t NOALLOC_BYTES = NOALLOC_W_BYTES + 2 * NOALLOC_KEYS_BYTES + NOALLOC_REC_BYTES;
+static_assert(NOALLOC_W_BYTES % 256 == 0 && NOALLOC_KEYS_BYTES % 256 == 0, "256-byte aligned sub-arrays");
+
+static __device__ __align__(256) double scratch[NOALLOC_BYTES / sizeof(double)];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+hipError_t g_scratch_err[NOALLOC_MAX_DEV] = {};
+bool g_scratch_done[NOALLOC_MAX_DEV] = {};
+
+// address of the current device's copy of `scratch` (looked up once per device)
+hipError_t noalloc_scratch_address(int device, void **ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= NOALLOC_MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *p = nullptr;
+        g_scratch_err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[device] = g_scratch_err[device] == hipSuccess ? p : nullptr;
+        g_scratch_done[device] = true;
+    }
+    *ptr = g_scratch_ptr[device];
+    return g_scratch_err[device];
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 extern "C" int shg_create(shg_ctx **out, void *hip_stream)
@@ -181,6 +219,9 @@ extern "C" int shg_create(shg_ctx **out, void *hip_stream)
             if (colon) *colon = 0;
         }
     }
+    // the fixed scratch of shg_pairs_noalloc (this device's copy); a failure is
+    // kept and reported by that entry point only
+    if (e == hipSuccess) c->noalloc_err = noalloc_scratch_address(c->device, &c->noalloc_scratch);
     std::vector<double> tab((size_t)BOYS_NPTS * BOYS_STRIDE);
     build_boys_table(tab.data());
     if (e == hipSuccess) e = hipMalloc((void **)&c->boys, tab.size() * sizeof(double));
@@ -402,6 +443,30 @@ extern "C" int shg_pairs_deriv(shg_ctx *c, const shg_shells *sh, shg_op op, doub
         return gcoulomb_pairs(c, "shg_pairs_deriv", omega, sh, pairs, n, out_off, out, dout);
     }
     return pairs_common(c, sh, op, omega, pairs, n, out_off, out, dout, true);
+}
+
+extern "C" int shg_pairs_noalloc(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
+                                 int64_t n, const int64_t *out_off, double *out, double *dout)
+{
+    const char *what = "shg_pairs_noalloc";
+    if (!c) return SHG_EINVAL;
+    const bool deriv = dout != nullptr;
+    int rc = pairs_validate(c, what, sh, op, omega, pairs, n, out_off, out, dout, deriv);
+    if (rc || n == 0) return rc;
+    if (n > SHG_NOALLOC_MAX_PAIRS)
+        return set_err(c, SHG_EINVAL, "%s: n = %lld exceeds SHG_NOALLOC_MAX_PAIRS = %d", what, (long long)n,
+                       SHG_NOALLOC_MAX_PAIRS);
+    if (sh->nprim_total > SHG_NOALLOC_MAX_PRIMS)
+        return set_err(c, SHG_EINVAL, "%s: nprim_total = %lld exceeds SHG_NOALLOC_MAX_PRIMS = %d", what,
+                       (long long)sh->nprim_total, SHG_NOALLOC_MAX_PRIMS);
+    if (c->noalloc_err != hipSuccess || !c->noalloc_scratch)
+        return set_err(c, SHG_EDEVICE, "%s: no address for the fixed scratch array: %s", what,
+                       hipGetErrorString(c->noalloc_err != hipSuccess ? c->noalloc_err : hipErrorInvalidSymbol));
+    char *base = (char *)c->noalloc_scratch;
+    PairScratch ps{(double *)base, (int32_t *)(base + NOALLOC_W_BYTES),
+                   (int32_t *)(base + NOALLOC_W_BYTES + NOALLOC_KEYS_BYTES),
+                   (PairRec *)(base + NOALLOC_W_BYTES + 2 * NOALLOC_KEYS_BYTES)};
+    return pairs_run(c, what, sh, op, omega, pairs, n, out_off, out, dout, deriv, ps);
 }
 
 extern "C" int shg_profile_enable(shg_ctx *c, int on)

@@ -65,6 +65,8 @@ struct shg_ctx {
     int32_t *bins = nullptr;         // [2][NBINS_MAX + 1]: histogram, then cursors
     int32_t *err = nullptr;          // device error flag
     int32_t *host_rb = nullptr;      // pinned read-back: class starts + error
+    void *noalloc_scratch = nullptr;  // this device's fixed scratch (shg_pairs_noalloc)
+    hipError_t noalloc_err = hipSuccess;
     char msg[512] = {0};
 };
 

@@ -21,7 +21,7 @@ EXPORTS = ("shg_create", "shg_destroy", "shg_last_error", "shg_pairs", "shg_pair
            "shg_set_tile_shape", "shg_get_tile_shape", "shg_autotune", "shg_tuning_save", "shg_tuning_load",
            "shg_profile_enable", "shg_profile_read", "shg_plan_create", "shg_plan_execute",
            "shg_plan_autotune", "shg_plan_set_mode", "shg_plan_mode", "shg_plan_destroy",
-           "shg_plan_stats", "shg_plan_kernel_ms", "shg_plan_skipped", "shg_plan_tile_order", "shg_set_aab_chunk", "shg_plan_time_kernels", "shg_plan_kernel_time", "shg_plan_set_tile_order", "shg_set_pairs",
+           "shg_plan_stats", "shg_plan_kernel_ms", "shg_plan_skipped", "shg_plan_tile_order", "shg_pairs_noalloc", "shg_set_aab_chunk", "shg_plan_time_kernels", "shg_plan_kernel_time", "shg_plan_set_tile_order", "shg_set_pairs",
            "shg_plan_create_screened", "shg_mlp_create", "shg_mlp_destroy", "shg_mlp_params", "shg_mlp_set_norm",
            "shg_mlp_set_margin", "shg_mlp_set_scope", "shg_mlp_train_step", "shg_mlp_grad", "shg_mlp_predict", "shg_mlp_save",
            "shg_mlp_load", "shg_screen_features", "shg_block_logmax")
@@ -70,6 +70,8 @@ def load_library(path: str = LIB_PATH):
     lib.shg_pairs_deriv.restype = C.c_int
     lib.shg_aab.argtypes = [P, C.POINTER(ShgShells), C.POINTER(ShgShells), P, C.c_int64, P, P, P]
     lib.shg_aab.restype = C.c_int
+    lib.shg_pairs_noalloc.argtypes = [P, C.POINTER(ShgShells), C.c_int, C.c_double, P, C.c_int64, P, P, P]
+    lib.shg_pairs_noalloc.restype = C.c_int
     lib.shg_set_pairs.argtypes = [P, C.POINTER(ShgSets), C.c_int, C.c_double, P, C.c_int64, P, P, P]
     lib.shg_set_pairs.restype = C.c_int
     lib.shg_set_aab_chunk.argtypes = [P, C.c_int64]
@@ -265,6 +267,13 @@ class Engine:
         self._check(self.lib.shg_set_pairs(self.ctx, C.byref(dst.c), OPS[op], float(omega), _ptr(set_pairs), n,
                                            _ptr(out_off), _ptr(out), _ptr(dout)))
 
+    def pairs_noalloc(self, dsh: DeviceShells, op: str, omega: float, pairs, out_off, out, dout=None):
+        """shg_pairs_noalloc: shg_pairs / shg_pairs_deriv with the library's fixed
+        scratch (no allocation in the call)."""
+        n = int(pairs.shape[0])
+        self._check(self.lib.shg_pairs_noalloc(self.ctx, C.byref(dsh.c), OPS[op], float(omega), _ptr(pairs), n,
+                                               _ptr(out_off), _ptr(out), _ptr(dout)))
+
     def pairs_r2n(self, dsh: DeviceShells, nr: int, pairs, out_off, out, dout=None):
         """shg_pairs_r2n: (a|r_a^{2n}|b) (and d/dR_a with `dout`) on device tensors."""
         n = int(pairs.shape[0])
@@ -298,6 +307,7 @@ class Engine:
 
 
 PLAN_PERSISTENT = 1
+NOALLOC_MAX_PAIRS = 1 << 20     # SHG_NOALLOC_MAX_PAIRS
 PLAN_NO_GRAPH = 2
 
 
