@@ -35,6 +35,7 @@ extern "C" int shgm_pairs(int32_t nshell, const double *center, const int32_t *l
         static const pair_fn *tabs[5] = {hm_table_op0(), hm_table_op1(), hm_table_op2(), hm_table_op3(),
                                          hm_table_op4()};
         pair_fn f = tabs[op][(l[a] * 5 + l[b]) * 2 + D];
+        if (!f) return -2;   // class not instantiated in this build
         f(exps + prim_off[a], w.data() + prim_off[a], nprim[a], exps + prim_off[b], w.data() + prim_off[b],
           nprim[b], X, omega, tab.data(), out + out_off[i], dout ? dout + 3 * out_off[i] : nullptr);
     }
