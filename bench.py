@@ -408,6 +408,60 @@ def main():
     print(json.dumps(res), flush=True)
 
 
+def family_set_extra(eng, shg, inputs, np, torch, natoms, density, kinds, cutoff, steps):
+    """Coulomb integrals + d/dR_A of MOLOPT family sets (Tables S2-S5) for atoms at
+    `density` (per bohr^3) in a cube, all ordered atom pairs within `cutoff`:
+    shg_set_pairs against shg_pairs_deriv on every function pair of the same set
+    pairs (the functions taken as shells)"""
+    from paper_1701_06588_amd import basis_molopt as bm
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(1006)
+    side = (natoms / density) ** (1.0 / 3.0)
+    pos = rng.uniform(0.0, side, size=(natoms, 3))
+    names = [kinds[i % len(kinds)] for i in range(natoms)]
+    st = bm.make_sets(pos, names)
+    sp = np.ascontiguousarray(inputs.atom_pairs_within(pos, cutoff), np.int32)
+    nsgf = st.nsgf()
+    sz = nsgf[sp[:, 0]] * nsgf[sp[:, 1]]
+    off = np.zeros(len(sz), np.int64)
+    off[1:] = np.cumsum(sz[:-1])
+    tot = int(sz.sum())
+    ds = eng.sets(st)
+    tsp = torch.as_tensor(sp, device=dev)
+    too = torch.as_tensor(off, device=dev)
+    out = torch.empty(tot, dtype=torch.float64, device=dev)
+    dout = torch.empty(3 * tot, dtype=torch.float64, device=dev)
+    ms_set, _ = timed(eng, lambda: eng.set_pairs(ds, "coulomb", 0.0, tsp, too, out, dout), steps, 1)
+    # the same function pairs through the shell path
+    sh, first = st.as_shells()
+    na = st.nfun[sp[:, 0]].astype(np.int64)
+    nb = st.nfun[sp[:, 1]].astype(np.int64)
+    cnt = na * nb
+    rep = np.repeat(np.arange(len(sp)), cnt)
+    local = np.arange(int(cnt.sum())) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    fa = first[sp[rep, 0]] + local // nb[rep]
+    fb = first[sp[rep, 1]] + local % nb[rep]
+    fp = np.ascontiguousarray(np.stack([fa, fb], axis=1), np.int32)
+    fsz = (2 * sh.l[fp[:, 0]].astype(np.int64) + 1) * (2 * sh.l[fp[:, 1]].astype(np.int64) + 1)
+    foff = np.zeros(len(fsz), np.int64)
+    foff[1:] = np.cumsum(fsz[:-1])
+    assert int(fsz.sum()) == tot
+    dsh = eng.shells(sh)
+    tfp = torch.as_tensor(fp, device=dev)
+    tfo = torch.as_tensor(foff, device=dev)
+    ms_sh, _ = timed(eng, lambda: eng.pairs(dsh, "coulomb", 0.0, tfp, tfo, out, dout), steps, 1)
+    nbytes = 4 * tot * 8 + 16 * len(sp)
+    del out, dout
+    torch.cuda.empty_cache()
+    return {"workload": f"{natoms} atoms ({'/'.join(kinds)}) at {density} bohr^-3, ordered atom pairs within "
+                        f"{cutoff} bohr, Coulomb values + d/dR_A",
+            "set_pairs": len(sp), "function_pairs": len(fp), "elements": tot,
+            "set_path_ms": round(ms_set, 4), "shell_path_ms": round(ms_sh, 4),
+            "speedup_set_over_shells": round(ms_sh / ms_set, 3),
+            "function_pair_blocks_per_s": round(len(fp) / (ms_set / 1e3), 1),
+            "hbm_frac": round(nbytes / (ms_set / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def run_extras(args, eng, shg, inputs, workmodel, np, torch):
     dev = torch.device("cuda")
     extra = {}
@@ -528,6 +582,13 @@ def run_extras(args, eng, shg, inputs, workmodel, np, torch):
     del o3, d3, tri3, oo3
     torch.cuda.empty_cache()
 
+    # ---- family sets on the paper's MOLOPT data: set path vs the same functions as shells ----
+    log("extra: MOLOPT family sets")
+    extra["molopt_sets"] = {}
+    for name, natoms, dens, kinds, cut in (("water", 12000, 0.0148, ("O-DZVP", "H-DZVP", "H-DZVP"), 10.0),
+                                           ("copper", 4000, 0.0126, ("Cu-DZVP",), 9.0)):
+        extra["molopt_sets"][name] = family_set_extra(eng, shg, inputs, np, torch, natoms, dens, kinds, cut, steps)
+
     # ---- 5000-atom screening workload: bound vs bound + trained network at the budget ----
     from paper_1701_06588_amd import screen
     if os.path.exists(screen.MODEL):
@@ -548,8 +609,9 @@ def run_extras(args, eng, shg, inputs, workmodel, np, torch):
         for op in ops5:
             ms_pl, _ = timed(eng, lambda: eng.pairs(dsh5, op, w5.omega[op], p5, oo5, ref5), 3, 1)
             abl["variants"].setdefault("plain", {})[op] = {"ms": round(ms_pl, 4)}
-            for vname, model in (("bound", None), ("bound+mlp", mlp)):
-                pl = shg.Plan(eng, dsh5, op, w5.omega[op], p5, oo5, got5, None, shg.PLAN_PERSISTENT, tau=tau5,
+            for vname, model, fl in (("bound", None, 0), ("bound+mlp", mlp, 0),
+                                     ("bound, compacting stage", None, shg.PLAN_COMPACT)):
+                pl = shg.Plan(eng, dsh5, op, w5.omega[op], p5, oo5, got5, None, shg.PLAN_PERSISTENT | fl, tau=tau5,
                               mlp=model)
                 pl.set_tile_order(args.tile_order if args.tile_order != "auto" else "alternating")
                 ms_v, _ = timed(eng, pl.execute, 3, 1)

@@ -232,6 +232,7 @@ int shg_set_aab_chunk(shg_ctx *ctx, int64_t chunk);
  *          SHG_PLAN_NO_GRAPH    enqueue the kernels on every execute */
 #define SHG_PLAN_PERSISTENT 1u
 #define SHG_PLAN_NO_GRAPH   2u
+#define SHG_PLAN_COMPACT    4u   /* screened plans only: see shg_plan_create_screened */
 typedef struct shg_plan shg_plan;
 int  shg_plan_create(shg_ctx *ctx, const shg_shells *sh, shg_op op, double omega,
                      const int32_t *pairs, int64_t n, const int64_t *out_off,
@@ -247,12 +248,13 @@ int  shg_plan_autotune(shg_plan *plan, int reps, double *ms_per_class, double *m
 int  shg_plan_set_mode(shg_plan *plan, int persistent);
 int  shg_plan_mode(const shg_plan *plan);     /* 0 per-class launches, 1 persistent */
 int  shg_plan_tile_order(const shg_plan *plan);  /* 0 heaviest first, 1 alternating ends, 2 round robin */
-/* fix the tile order of the persistent queue (0..2; screened plans 0..1)
+/* fix the tile order of the persistent queue (0..2; compacting screened plans 0..1)
  * without timing; re-records the graphs; synchronises the context stream */
 int  shg_plan_set_tile_order(shg_plan *plan, int order);
 /* ids of the pairs the last execution of a screened plan skipped, written to
- * the host array ids (capacity cap, nullable); returns how many there are (0
- * for unscreened plans). Synchronises the context stream. */
+ * the host array ids (capacity cap, nullable; in no particular order); returns
+ * how many there are (0 for unscreened plans). Synchronises the context
+ * stream. */
 int64_t shg_plan_skipped(const shg_plan *plan, int32_t *ids, int64_t cap);
 /* number of pairs a plan evaluates (a screened plan: at its last execution)
  * and their algorithmic bytes (8 (2la+1)(2lb+1)(1 or 4) + 16 per pair); host
@@ -339,9 +341,17 @@ int shg_plan_create_r2n(shg_ctx *ctx, const shg_shells *sh, int nr, const int32_
  * features inside its training range) predicts, plus its margin, below
  * log10(tau). Skipped blocks (and their d/dR_a blocks) are set to zero in the
  * same execution; kept blocks are those of the plain path. The execution
- * (graph replay) reads nothing back to the host: shell preparation, bound and
- * model inference, a scan compacting the kept class-sorted pair records, the
- * tile queue built from the kept counts, the zeroing and the persistent kernel.
+ * (graph replay) reads nothing back to the host. Two ways to run it:
+ *   default           the persistent kernel evaluates the bound of each pair
+ *                     of its tile (or reads the model's decision) before the
+ *                     radial sum; a skipped pair gets no primitive work and
+ *                     its block is stored as zeros by the tile itself. Best
+ *                     when few pairs drop out.
+ *   SHG_PLAN_COMPACT  a screening stage (bound or model, a scan compacting the
+ *                     kept class-sorted pair records, a tile queue built from
+ *                     the kept counts, the skipped blocks zeroed) runs before
+ *                     the persistent kernel, which sees kept pairs only. Best
+ *                     when most pairs drop out.
  * The model, if any, must outlive the plan. Operators SHG_OVERLAP..SHG_GAUSS;
  * tau > 0. Creation executes once; *n_skipped (host, nullable) receives the
  * number of pairs that execution skipped. */

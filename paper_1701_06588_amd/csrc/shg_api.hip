@@ -252,6 +252,7 @@ extern "C" void shg_destroy(shg_ctx *c)
     (void)hipFree(c->rec);
     (void)hipFree(c->bins);
     (void)hipFree(c->stats);
+    (void)hipFree(c->bound_tab);
     (void)hipFree(c->set_w);
     (void)hipFree(c->set_osz);
     (void)hipFree(c->set_nsgf);

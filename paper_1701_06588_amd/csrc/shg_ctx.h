@@ -55,6 +55,7 @@ struct shg_ctx {
     int64_t aab_chunk = (int64_t)1 << 17;          // triples per (class, chunk) work item
     hipEvent_t aab_ev[AAB_NSTREAM] = {};          // [0] fork from the context stream, [w] join of side stream w
     double *stats = nullptr; size_t stats_cap = 0;  // per-shell screening statistics
+    void *bound_tab = nullptr;       // constants of the analytic bound (device)
     // family sets (shg_set_pairs): folded weights, radial-scratch sizes and
     // offsets, spherical functions per set, l-block items, radial scratch
     double *set_w = nullptr; size_t set_w_cap = 0;
@@ -139,12 +140,16 @@ void r2n_radial_range(hipStream_t s, int cls, bool deriv, const shg_shells *sh, 
 int gcoulomb_pairs(shg_ctx *c, const char *what, double omega, const shg_shells *sh, const int32_t *pairs, int64_t n,
                    const int64_t *out_off, double *out, double *dout);
 // screening stage of a screened plan (shg_screen.hip): per-shell statistics
-// from the folded weights, then keep[i] (0: skip) for the n class-sorted
-// records; kernels only, graph-capturable; work: n * 15 floats with a model
+// from the folded weights, then (keep non-NULL) keep[i] (0: skip) for the n
+// class-sorted records, the kept flags counted into bsum[i / 4096] (bsum
+// nullable, zeroed by the caller); kernels only, graph-capturable; work: n * 15
+// floats with a model
 int plan_screen_enqueue(shg_ctx *c, hipStream_t s, const shg_shells *sh, const double *w, double *stats,
                         const PairRec *rec, int64_t n, int nops, const int *ops, const double *omegas, int deriv,
-                        double tau, shg_mlp *mlp, float *work, int32_t *keep);
+                        double tau, shg_mlp *mlp, float *work, uint8_t *keep, int32_t *bsum);
 size_t plan_screen_stats_doubles(int nshell);
+// uploads the bound's constants (once per context; not during stream capture)
+int screen_prepare(shg_ctx *c);
 // whether a model predicts operator op (and, with deriv, the d/dR_a blocks too)
 bool mlp_covers(const shg_mlp *m, int op, int deriv);
 

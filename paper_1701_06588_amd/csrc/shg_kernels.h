@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "shg_bound.h"
 #include "shg_math.h"
 
 namespace shg {
@@ -62,6 +63,16 @@ struct TileArgs {
     int64_t ybase, ys, yoff;
     const int64_t *ooff;
     int tstride;
+    // in-kernel screening (screened plans; two-center mode): with sstat set, a
+    // pair whose analytic bound (shg_bound.h, per-shell statistics sstat) is
+    // below stau -- or, with skeep set, whose decision flag skeep[pos] is 0 --
+    // gets zero radial terms, so its block and d/dR_a blocks are written as
+    // zeros; its sorted position is appended to sskip (count in *sskip_n)
+    const double *sstat;
+    const BoundTab *sbt;
+    const uint8_t *skeep;
+    int32_t *sskip, *sskip_n;
+    double stau;
 };
 
 // tile shape: TP pairs (64, 128 or 256) and rows_pp block rows per LDS pass
@@ -187,6 +198,32 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
         const int G = TILE_THREADS / TP;
         const int i = tid / G, g = tid - (tid / G) * G;
         const bool live = i < tcount;
+        bool skip = false;
+        if (a.sstat) {
+            // screening: one thread per pair decides (bound, or the model's flag)
+            // before any radial work; the flags pass through the staging area,
+            // which is free until phase 2
+            int *sSkip = (int *)sT;
+            for (int q = tid; q < tcount; q += TILE_THREADS) {
+                bool sk;
+                if (a.skeep) {
+                    sk = a.skeep[tstart + q] == 0;
+                } else {
+                    const PairRec r = a.rec[tstart + q];
+                    const double Y0 = a.center[3 * r.a] - a.center[3 * r.b];
+                    const double Y1 = a.center[3 * r.a + 1] - a.center[3 * r.b + 1];
+                    const double Y2 = a.center[3 * r.a + 2] - a.center[3 * r.b + 2];
+                    double vb, Rr, rm;
+                    sk = shell_pair_bound(LA, LB, a.sstat + (size_t)r.a * STAT, a.sstat + (size_t)r.b * STAT,
+                                          fma(Y0, Y0, fma(Y1, Y1, Y2 * Y2)), a.op, a.omega, D ? 1 : 0, a.sbt, &vb,
+                                          &Rr, &rm) < a.stau;
+                }
+                if (sk) a.sskip[atomicAdd(a.sskip_n, 1)] = (int32_t)(tstart + q);
+                sSkip[q] = sk ? 1 : 0;
+            }
+            __syncthreads();
+            skip = live && sSkip[i] != 0;
+        }
         const PairRec rc = a.rec[tstart + (live ? i : 0)];
         const int sa = rc.a, sb = rc.b;
         const double X0 = a.center[3 * sa] - a.center[3 * sb];
@@ -195,7 +232,8 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
         const double R2 = fma(X0, X0, fma(X1, X1, X2 * X2));   // fixed rounding order
         const int64_t oa = a.prim_off[sa], ob = a.prim_off[sb];
         const int kb = a.nprim[sb];
-        const int P = live ? a.nprim[sa] * kb : 0;
+        // a skipped pair gets no primitive work: its O^(k) stay zero, and so does its block
+        const int P = live && !skip ? a.nprim[sa] * kb : 0;
         double O[PK::NK];
 #pragma unroll
         for (int k = 0; k < PK::NK; ++k) O[k] = 0.0;

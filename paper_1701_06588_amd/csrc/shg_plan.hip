@@ -8,10 +8,13 @@
 //   per-class   the per-class k_tile launches of the plain path, graph-captured
 //   persistent  one k_persist launch over a tile work queue
 // A screened plan decides on every execution, on the device, which pairs are
-// evaluated: analytic bound (and learned predictor) per pair, a scan that
-// compacts the kept class-sorted records, the tile queue built from the kept
-// counts, the skipped blocks zeroed, then the persistent kernel, which reads
-// the number of tiles from device memory. Nothing is read back to the host.
+// evaluated; nothing is read back to the host. By default the persistent
+// kernel tests each pair's analytic bound (or reads the learned predictor's
+// decision) before its radial sum and stores a skipped pair's block as zeros.
+// With SHG_PLAN_COMPACT a stage runs first: bound or predictor per pair, a
+// scan that compacts the kept class-sorted records, the tile queue built from
+// the kept counts, the skipped blocks zeroed; the persistent kernel then reads
+// the number of tiles from device memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,19 +38,21 @@ struct shg_plan {
     int mode = 0;                     // 0 per-class launches, 1 persistent
     int qorder = 1;                   // tile order: 0 heaviest first, 1 alternating ends, 2 round robin
     int32_t *order = nullptr;         // class-sorted pair ids (plan-owned)
-    PairRec *rec = nullptr;           // class-sorted pair records (plan-owned; screened: the kept ones)
+    PairRec *rec = nullptr;           // class-sorted pair records (plan-owned; compacting: the kept ones)
     double *w = nullptr;              // folded weights (plan-owned)
     QTile *queue = nullptr;
     int ntiles = 0;                   // screened: the most tiles a queue can hold
     int *counter = nullptr;           // [0] tile counter; screened plans: the meta block below
-    // screening on the device (screened plans); meta: [0] tile counter, [1] tiles,
-    // [2] kept, [3] skipped, [META_KS + c] kept start of class c, [META_TS + k]
-    // first tile of the k-th class of the queue order
+    // screening on the device (screened plans); meta: [0] tile counter; in-kernel
+    // mode [4] skipped; compacting mode [1] tiles, [2] kept, [3] skipped,
+    // [META_KS + c] kept start of class c, [META_TS + k] first tile of the k-th
+    // class of the queue order
     int screened = 0;
+    int compact = 0;                  // screened: compaction stage (else in-kernel skipping)
     double tau = 0;
     shg_mlp *mlp = nullptr;
     PairRec *rec_all = nullptr;       // class-sorted records of every pair
-    int32_t *keep = nullptr;          // [n] decision per sorted position
+    uint8_t *keep = nullptr;          // [n] decision per sorted position
     int32_t *bsum = nullptr;          // [2][nblk + 1]: kept per scan block, exclusive scan
     int32_t *skip = nullptr;          // [n] sorted positions of the skipped pairs
     double *stats = nullptr;          // per-shell screening statistics
@@ -82,6 +87,14 @@ static TileArgs plan_tile_args(const shg_plan *p)
 {
     TileArgs ta{p->rec, p->order, p->sh.center, p->sh.nprim, p->sh.prim_off, p->sh.exps, p->w, p->ctx->boys, p->out,
                 p->dout, p->omega, p->op};
+    if (p->screened && !p->compact) {
+        ta.sstat = p->stats;
+        ta.sbt = (const BoundTab *)p->ctx->bound_tab;
+        ta.skeep = p->mlp ? p->keep : nullptr;
+        ta.sskip = p->skip;
+        ta.sskip_n = p->counter + 4;
+        ta.stau = p->tau;
+    }
     if (plan_mono(p->op)) {
         ta.triples = p->pairs;
         ta.tstride = 2;
@@ -123,30 +136,12 @@ struct ScreenShape {
     int32_t qorder;   // 0 heaviest first, 1 alternating ends
 };
 
-// kept positions per scan block of SCAN_BLK sorted positions
-__global__ __launch_bounds__(SCAN_TPB) void k_keep_count(int64_t n, const int32_t *keep, int32_t *bsum)
-{
-    __shared__ int32_t red[SCAN_TPB / 64];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_BLK;
-    int cnt = 0;
-    for (int it = 0; it < SCAN_ITEMS; ++it) {
-        const int64_t i = base + (int64_t)it * SCAN_TPB + threadIdx.x;
-        if (i < n) cnt += keep[i] != 0;
-    }
-    for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-// one workgroup: exclusive scan of the block counts into bscan, the kept start
-// of every class, the tile counts of the queue (classes in queue order) and
-// the meta block; clears the tile counter
-__global__ __launch_bounds__(256) void k_keep_scan(ScreenShape ss, const int32_t *keep, const int32_t *bsum,
-                                                   int32_t *bscan, int32_t *meta)
+// one workgroup: exclusive scan of the kept counts of the scan blocks (written
+// by the screening stage), the kept and skipped totals, the kept start of the
+// classes that begin at the end of the list; clears the tile counter
+__global__ __launch_bounds__(256) void k_keep_scan(ScreenShape ss, const int32_t *bsum, int32_t *bscan, int32_t *meta)
 {
     __shared__ int32_t part[256];
-    __shared__ int32_t ks[NCLASS + 1];
     const int t = threadIdx.x, nb = ss.nblk;
     const int per = (nb + 255) / 256;
     const int lo = min(nb, t * per), hi = min(nb, lo + per);
@@ -161,63 +156,45 @@ __global__ __launch_bounds__(256) void k_keep_scan(ScreenShape ss, const int32_t
             part[i] = run;
             run += v;
         }
+        part[0] = run;   // (thread 0 already holds its own prefix, 0)
     }
     __syncthreads();
-    acc = part[t];
+    const int32_t total = part[0];
+    acc = t == 0 ? 0 : part[t];
     for (int b = lo; b < hi; ++b) {
         bscan[b] = acc;
         acc += bsum[b];
     }
-    if (t == 255) bscan[nb] = acc;
-    // kept positions before the first position of each class
-    if (t <= NCLASS) {
-        const int32_t pos = ss.cls_all[t];
-        const int b = pos / SCAN_BLK;
-        int32_t k = 0;
-        if (b < nb) {
-            const int owner = per > 0 ? b / per : 0;
-            k = part[owner];
-            for (int q = owner * per; q < b; ++q) k += bsum[q];
-            for (int32_t i = b * SCAN_BLK; i < pos; ++i) k += keep[i] != 0;
-        } else {
-            k = part[255];
-            for (int q = 255 * per; q < nb; ++q) k += bsum[q];
-        }
-        ks[t] = k;
-        meta[META_KS + t] = k;
-    }
-    __syncthreads();
+    if (t <= NCLASS && ss.cls_all[t] >= ss.cls_all[NCLASS]) meta[META_KS + t] = total;
     if (t == 0) {
-        int32_t tiles = 0;
-        for (int q = 0; q < NCLASS; ++q) {
-            const int c = ss.cls_seq[q];
-            meta[META_TS + q] = tiles;
-            tiles += (ks[c + 1] - ks[c] + 63) / 64;
-        }
-        meta[META_TS + NCLASS] = tiles;
+        bscan[nb] = total;
         meta[0] = 0;
-        meta[1] = tiles;
-        meta[2] = ks[NCLASS];
-        meta[3] = ss.cls_all[NCLASS] - ks[NCLASS];
+        meta[2] = total;
+        meta[3] = ss.cls_all[NCLASS] - total;
     }
 }
 
 // stable compaction: kept sorted position i -> rec[kept before i] = rec_all[i];
-// skipped position i -> skip[skipped before i] = i. A thread owns SCAN_ITEMS
-// consecutive positions of its block.
-__global__ __launch_bounds__(SCAN_TPB) void k_compact(int64_t n, const int32_t *keep, const int32_t *bscan,
-                                                      const PairRec *rec_all, PairRec *rec, int32_t *skip)
+// skipped position i -> skip[skipped before i] = i; the kept start of every
+// class that begins inside the list. A thread owns SCAN_ITEMS consecutive
+// positions of its block (one 16-byte load of their flags).
+__global__ __launch_bounds__(SCAN_TPB) void k_compact(int64_t n, ScreenShape ss, const uint8_t *keep,
+                                                      const int32_t *bscan, const PairRec *rec_all, PairRec *rec,
+                                                      int32_t *skip, int32_t *meta)
 {
+    static_assert(SCAN_ITEMS == 16, "one 16-byte load of flags per thread");
     __shared__ int32_t wsum[SCAN_TPB / 64];
     const int64_t base = (int64_t)blockIdx.x * SCAN_BLK + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int32_t flags = 0, cnt = 0;
+    uint32_t flags = 0;
+    if (base + SCAN_ITEMS <= n) {
+        const uint4 v = *(const uint4 *)(keep + base);
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int it = 0; it < SCAN_ITEMS; ++it) {
-        const int64_t i = base + it;
-        const int k = i < n ? (keep[i] != 0) : 0;
-        flags |= k << it;
-        cnt += k;
+        for (int q = 0; q < 16; ++q) flags |= (((w4[q >> 2] >> (8 * (q & 3))) & 0xffu) != 0 ? 1u : 0u) << q;
+    } else {
+        for (int q = 0; q < 16 && base + q < n; ++q) flags |= (keep[base + q] != 0 ? 1u : 0u) << q;
     }
+    const int cnt = __popc(flags);
     // inclusive scan of the per-thread counts within the wave, then across waves
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int32_t inc = cnt;
@@ -229,31 +206,48 @@ __global__ __launch_bounds__(SCAN_TPB) void k_compact(int64_t n, const int32_t *
     __syncthreads();
     int32_t wbase = 0;
     for (int q = 0; q < wv; ++q) wbase += wsum[q];
-    int32_t kept = bscan[blockIdx.x] + wbase + inc - cnt;   // kept before this thread's first position
-    int64_t skipped = base - kept;
-#pragma unroll
-    for (int it = 0; it < SCAN_ITEMS; ++it) {
-        const int64_t i = base + it;
+    const int32_t kept0 = bscan[blockIdx.x] + wbase + inc - cnt;   // kept before this thread's first position
+    // kept starts of the classes beginning in this thread's positions
+    for (int c = 0; c <= NCLASS; ++c) {
+        const int32_t pos = ss.cls_all[c];
+        if (pos >= base && pos < base + SCAN_ITEMS && pos < n)
+            meta[META_KS + c] = kept0 + __popc(flags & ((1u << (pos - base)) - 1u));
+    }
+    int32_t kept = kept0;
+    int64_t skipped = base - kept0;
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        const int64_t i = base + q;
         if (i >= n) break;
-        if ((flags >> it) & 1) rec[kept++] = rec_all[i];
+        if ((flags >> q) & 1u) rec[kept++] = rec_all[i];
         else skip[skipped++] = (int32_t)i;
     }
 }
 
 // tile queue of the kept pairs: 64-pair tiles, classes in queue order
-// (heaviest first; alternately from the two ends with qorder 1)
-__global__ void k_build_queue(ScreenShape ss, const int32_t *meta, int max_tiles, QTile *q)
+// (heaviest first; alternately from the two ends with qorder 1); the tile
+// count goes to meta[1] for the persistent kernel
+__global__ void k_build_queue(ScreenShape ss, int32_t *meta, int max_tiles, QTile *q)
 {
-    const int ntiles = meta[1];
+    int32_t ks[NCLASS + 1], ts[NCLASS + 1];
+#pragma unroll
+    for (int c = 0; c <= NCLASS; ++c) ks[c] = meta[META_KS + c];
+    int32_t ntiles = 0;
+#pragma unroll
+    for (int k = 0; k < NCLASS; ++k) {
+        const int c = ss.cls_seq[k];
+        ts[k] = ntiles;
+        ntiles += (ks[c + 1] - ks[c] + 63) / 64;
+    }
+    ts[NCLASS] = ntiles;
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta[1] = ntiles;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < max_tiles; j += gridDim.x * blockDim.x) {
         if (j >= ntiles) break;
         const int src = ss.qorder == 1 ? ((j & 1) ? ntiles - 1 - (j >> 1) : (j >> 1)) : j;
         int k = 0;
-        while (k + 1 < NCLASS && meta[META_TS + k + 1] <= src) ++k;
+        while (k + 1 < NCLASS && ts[k + 1] <= src) ++k;
         const int c = ss.cls_seq[k];
-        const int32_t u = src - meta[META_TS + k];
-        const int32_t kept_c = meta[META_KS + c + 1] - meta[META_KS + c];
-        q[j] = QTile{c, min(64, kept_c - 64 * u), (int64_t)meta[META_KS + c] + 64 * (int64_t)u};
+        const int32_t u = src - ts[k];
+        q[j] = QTile{c, min(64, ks[c + 1] - ks[c] - 64 * u), (int64_t)ks[c] + 64 * (int64_t)u};
     }
 }
 
@@ -289,20 +283,32 @@ static ScreenShape plan_screen_shape(const shg_plan *p)
     return ss;
 }
 
-// screening stage: decisions, compaction, tile queue, skipped blocks zeroed
+// screening stage. In-kernel mode: per-shell statistics (and with a model the
+// decision flags), skip count and tile counter cleared; the persistent kernel
+// decides per pair. Compaction mode: decisions, compaction, tile queue, skipped
+// blocks zeroed.
 static int plan_screen_stage(shg_plan *p, hipStream_t s)
 {
     shg_ctx *c = p->ctx;
     const int64_t n = p->n;
     if (n == 0) return 0;
-    int rc = plan_screen_enqueue(c, s, &p->sh, p->w, p->stats, p->rec_all, n, 1, &p->op, &p->omega, p->deriv, p->tau,
-                                 p->mlp, p->swork, p->keep);
-    if (rc) return rc;
+    if (!p->compact) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 8);
+        int rc = plan_screen_enqueue(c, s, &p->sh, p->w, p->stats, p->rec_all, n, 1, &p->op, &p->omega, p->deriv,
+                                     p->tau, p->mlp, p->swork, p->mlp ? p->keep : nullptr, nullptr);
+        if (rc) return rc;
+        HIP_TRY(c, hipGetLastError());
+        return 0;
+    }
     const ScreenShape ss = plan_screen_shape(p);
     int32_t *bscan = p->bsum + ss.nblk + 1;
-    hipLaunchKernelGGL(k_keep_count, dim3(ss.nblk), dim3(SCAN_TPB), 0, s, n, p->keep, p->bsum);
-    hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(256), 0, s, ss, p->keep, p->bsum, bscan, p->counter);
-    hipLaunchKernelGGL(k_compact, dim3(ss.nblk), dim3(SCAN_TPB), 0, s, n, p->keep, bscan, p->rec_all, p->rec, p->skip);
+    hipLaunchKernelGGL(k_fill_i32, dim3((ss.nblk + 1 + 255) / 256), dim3(256), 0, s, p->bsum, 0, ss.nblk + 1);
+    int rc = plan_screen_enqueue(c, s, &p->sh, p->w, p->stats, p->rec_all, n, 1, &p->op, &p->omega, p->deriv, p->tau,
+                                 p->mlp, p->swork, p->keep, p->bsum);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(256), 0, s, ss, p->bsum, bscan, p->counter);
+    hipLaunchKernelGGL(k_compact, dim3(ss.nblk), dim3(SCAN_TPB), 0, s, n, ss, p->keep, bscan, p->rec_all, p->rec,
+                       p->skip, p->counter);
     const unsigned qgrid = (unsigned)std::max(1, std::min((p->ntiles + 255) / 256, 1024));
     hipLaunchKernelGGL(k_build_queue, dim3(qgrid), dim3(256), 0, s, ss, p->counter, p->ntiles, p->queue);
     const unsigned zgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, 2048));
@@ -318,8 +324,8 @@ static void plan_launch_persist(const shg_plan *p, hipStream_t s, const TileArgs
     persist_occ_fn occ;
     if (p->deriv) persist_entry_d1(&f, &occ);
     else persist_entry_d0(&f, &occ);
-    // a screened plan's kernel reads the number of tiles from counter[1]
-    f(s, p->grid, p->smem, ta, p->queue, p->screened ? -1 : p->ntiles, p->counter);
+    // a compacting screened plan's kernel reads the number of tiles from counter[1]
+    f(s, p->grid, p->smem, ta, p->queue, p->screened && p->compact ? -1 : p->ntiles, p->counter);
 }
 
 // shell preparation and the stage before the evaluation kernels (radial terms
@@ -485,6 +491,9 @@ static int plan_create_impl(shg_ctx *c, const shg_shells *sh, int op, double ome
                             shg_plan **plan)
 {
     const bool deriv = dout != nullptr;
+    if (flags & ~(SHG_PLAN_PERSISTENT | SHG_PLAN_NO_GRAPH))
+        return set_err(c, SHG_EINVAL, "plan: flags 0x%x not known here (SHG_PLAN_COMPACT is for screened plans)",
+                       flags & ~(SHG_PLAN_PERSISTENT | SHG_PLAN_NO_GRAPH));
     // evaluate once through the plain path: validates the input and bins the pairs
     int rc = op == PLAN_OP_R2N ? shg_pairs_r2n(c, sh, nr, pairs, n, out_off, out, dout)
              : deriv           ? shg_pairs_deriv(c, sh, (shg_op)op, omega, pairs, n, out_off, out, dout)
@@ -570,10 +579,29 @@ static int plan_read_meta(const shg_plan *p, int64_t *kept, int64_t *skipped, in
     int32_t m[META_N];
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     HIP_TRY(c, hipMemcpy(m, p->counter, sizeof(m), hipMemcpyDeviceToHost));
-    if (kept) *kept = m[2];
-    if (skipped) *skipped = m[3];
-    if (ks)
-        for (int cls = 0; cls <= NCLASS; ++cls) ks[cls] = m[META_KS + cls];
+    if (p->compact) {
+        if (kept) *kept = m[2];
+        if (skipped) *skipped = m[3];
+        if (ks)
+            for (int cls = 0; cls <= NCLASS; ++cls) ks[cls] = m[META_KS + cls];
+        return 0;
+    }
+    // in-kernel mode: skip count in m[4], positions in p->skip
+    const int64_t ns = m[4];
+    if (kept) *kept = p->n - ns;
+    if (skipped) *skipped = ns;
+    if (ks) {
+        // kept per class = class size minus the skipped positions inside it
+        std::vector<int32_t> pos(ns);
+        if (ns > 0 && hipMemcpy(pos.data(), p->skip, ns * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return set_err(c, SHG_EDEVICE, "plan: read-back failed");
+        std::vector<int64_t> cnt(NCLASS, 0);
+        for (int32_t q : pos)
+            for (int cls = 0; cls < NCLASS; ++cls)
+                if (q >= p->cls_all[cls] && q < p->cls_all[cls + 1]) ++cnt[cls];
+        ks[0] = 0;
+        for (int cls = 0; cls < NCLASS; ++cls) ks[cls + 1] = ks[cls] + (p->cls_all[cls + 1] - p->cls_all[cls]) - cnt[cls];
+    }
     return 0;
 }
 
@@ -590,12 +618,13 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
     if (flags & SHG_PLAN_NO_GRAPH) return set_err(c, SHG_EINVAL, "%s: screened plans are always recorded", what);
     shg_plan *p = nullptr;
     int rc = shg_plan_create(c, sh, op, omega, pairs, n, out_off, out, dout,
-                             (flags | SHG_PLAN_PERSISTENT | SHG_PLAN_NO_GRAPH), &p);
+                             ((flags & ~SHG_PLAN_COMPACT) | SHG_PLAN_PERSISTENT | SHG_PLAN_NO_GRAPH), &p);
     if (rc) return rc;
     auto fail = [&](int code) { shg_plan_destroy(p); return code; };
     if (p->smem > (size_t)PERSIST_MAX_SMEM)
         return fail(set_err(c, SHG_EINVAL, "%s: the persistent kernel cannot take these tiles", what));
     p->screened = 1;
+    p->compact = (flags & SHG_PLAN_COMPACT) ? 1 : 0;
     p->mode = 1;
     p->tau = tau;
     p->mlp = mlp;
@@ -604,7 +633,7 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
     hipError_t e = hipSuccess;
     if (n > 0) {
         e = hipMalloc((void **)&p->rec_all, n * sizeof(PairRec));
-        if (e == hipSuccess) e = hipMalloc((void **)&p->keep, n * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc((void **)&p->keep, ((n + 15) / 16 * 16) * sizeof(uint8_t));
         if (e == hipSuccess) e = hipMalloc((void **)&p->skip, n * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc((void **)&p->bsum, 2 * (nb + 1) * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc((void **)&p->stats, plan_screen_stats_doubles(sh->nshell) * sizeof(double));
@@ -617,6 +646,7 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
         e = hipMalloc((void **)&p->counter, META_N * sizeof(int32_t));
     }
     if (e != hipSuccess) return fail(set_err(c, SHG_ENOMEM, "%s: %s", what, hipGetErrorString(e)));
+    if ((rc = screen_prepare(c))) return fail(rc);
     if ((rc = plan_capture(p))) return fail(rc);
     // the first execution zeroes the skipped blocks (the plain evaluation of the
     // creation wrote every block) and gives the skip count
@@ -717,15 +747,15 @@ extern "C" int shg_plan_autotune(shg_plan *p, int reps, double *ms_per_class, do
     };
     float t_class = 0, t_pers = 0;
     int rc = 0;
-    // a screened plan runs the persistent kernel over a queue built on the
-    // device in one of the first two orders
+    // a screened plan runs the persistent kernel only; a compacting one over a
+    // queue built on the device in one of the first two orders
     if (!p->screened && (rc = time_mode(0, &t_class))) return rc;
     const bool can_persist = p->smem <= (size_t)PERSIST_MAX_SMEM;
     if (can_persist) {
         // the persistent kernel with each tile order of the queue
         int best_q = p->qorder;
         float best = 0;
-        const int norders = p->screened ? 2 : 3;
+        const int norders = p->screened && p->compact ? 2 : 3;
         for (int qo = 0; qo < norders; ++qo) {
             p->qorder = qo;
             if ((rc = plan_build_queue(p))) return rc;
@@ -760,7 +790,7 @@ extern "C" int shg_plan_tile_order(const shg_plan *p) { return p ? p->qorder : S
 extern "C" int shg_plan_set_tile_order(shg_plan *p, int order)
 {
     if (!p) return SHG_EINVAL;
-    if (order < 0 || order > (p->screened ? 1 : 2))
+    if (order < 0 || order > (p->screened && p->compact ? 1 : 2))
         return set_err(p->ctx, SHG_EINVAL, "plan: tile order %d not available for this plan", order);
     HIP_TRY(p->ctx, hipStreamSynchronize(p->ctx->stream));
     p->qorder = order;
@@ -828,7 +858,10 @@ extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
     const TileArgs ta = plan_tile_args(p);
     double tot = 0;
     for (int r = 0; r < reps; ++r) {
-        if (p->mode >= 1) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, 1);
+        // in-kernel screening appends to the skip list: its count restarts too
+        if (p->mode >= 1)
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0,
+                               p->screened && !p->compact ? 8 : 1);
         HIP_TRY(c, hipEventRecord(e0, c->stream));
         plan_radial(p, c->stream);
         if (p->mode == 1) {

@@ -31,6 +31,7 @@
 #include <random>
 #include <vector>
 
+#include "shg_bound.h"
 #include "shg_ctx.h"
 
 using namespace shg;
@@ -43,8 +44,6 @@ constexpr int NPARAM = NH * NF + NH + NH * NH + NH + NH * NH + NH + NH + 1;   //
 // parameter offsets in the flat fp32 array
 constexpr int P_W1 = 0, P_B1 = P_W1 + NH * NF, P_W2 = P_B1 + NH, P_B2 = P_W2 + NH * NH, P_W3 = P_B2 + NH,
               P_B3 = P_W3 + NH * NH, P_W4 = P_B3 + NH, P_B4 = P_W4 + NH;
-constexpr int STAT = 32;        // doubles per shell in the statistics table
-constexpr int KB = 10;          // k = 0..9 moments
 
 // ---------------------------------------------------------------------------
 // per-shell statistics: alpha_min, alpha_max, sum|w|, Sf, Sc[k], So[k]
@@ -79,62 +78,20 @@ __global__ void k_shell_stats(int nshell, const int32_t *nprim, const int64_t *p
     }
 }
 
-struct BoundTab {
-    double cq[5][5][5];   // Cq(la, lb, j)
-};
 
-__device__ __forceinline__ double dfact_d(int n) { double f = 1; for (int i = n; i > 1; i -= 2) f *= i; return f; }
 
-// Analytic bound of one pair (a, b): returns the bound on max|block| and, with
-// deriv, on the d/dR_a elements too (their maximum); *vbound receives the
-// value bound alone. *R_out and *rmin_out receive R and the smallest reduced
-// exponent (features).
-__device__ double pair_bound(int a, int b, const double *center, const int32_t *l, const double *st, int op,
-                             double omega, int deriv, const BoundTab &bt, double *vbound, double *R_out,
-                             double *rmin_out)
+
+// Analytic bound of one pair (a, b) (shg_bound.h) with its l values read from
+// the shell table
+__device__ __forceinline__ double pair_bound(int a, int b, const double *center, const int32_t *l, const double *st,
+                                             int op, double omega, int deriv, const BoundTab *__restrict__ bt,
+                                             double *vbound, double *R_out, double *rmin_out)
 {
-    const int la = l[a], lb = l[b];
     const double X0 = center[3 * a] - center[3 * b], X1 = center[3 * a + 1] - center[3 * b + 1],
                  X2 = center[3 * a + 2] - center[3 * b + 2];
-    const double R2 = X0 * X0 + X1 * X1 + X2 * X2, R = sqrt(R2);
-    const double *sa = st + (size_t)a * STAT, *sb = st + (size_t)b * STAT;
-    const double rmin = sa[0] * sb[0] / (sa[0] + sb[0]);
-    const double PI_ = 3.141592653589793238462643383279502884;
-    // bound on |O^(k)| (k-th R^2-derivative of the contracted radial term)
-    auto obound = [&](int k) {
-        double ob;
-        if (op == OP_OVERLAP || op == OP_GAUSS) {
-            ob = pow(2.0, -1.5 - k) * sa[4 + KB + k] * sb[4 + KB + k];
-            if (op == OP_OVERLAP) ob *= pow(PI_, 1.5) * exp(-rmin * R2);
-            else ob *= PI_ * PI_ * PI_ * pow(omega, -1.5) * exp(-omega * rmin * R2 / (rmin + omega));
-        } else {
-            double nearb = 2.0 * pow(PI_, 2.5) * pow(2.0, -(k + 0.5)) / (2 * k + 1) * sa[4 + k] * sb[4 + k];
-            double farb = R > 0 ? 2.0 * PI_ * PI_ * PI_ * dfact_d(2 * k - 1) * pow(2.0, -(k + 1)) * sa[3] * sb[3] *
-                                      pow(R, -(2.0 * k + 1))
-                                : 1e300;
-            ob = fmin(nearb, farb) * (op == OP_ERFC ? 2.0 : 1.0);
-        }
-        return ob;
-    };
-    double bound = 0.0, dbound = 0.0;
-    const int jm = la < lb ? la : lb;
-    for (int j = 0; j <= jm; ++j) {
-        const int k = la + lb - j, pw = la + lb - 2 * j;
-        const double ok = obound(k);
-        bound += ok * bt.cq[la][lb][j] * (pw == 0 ? 1.0 : pow(R, (double)pw));
-        if (deriv) {
-            // d/dX_i [O^(k)(R^2) P_j(X)] = 2 X_i O^(k+1) P_j + O^(k) d_i P_j, with P_j homogeneous of
-            // degree pw and |P_j| <= Cq R^pw; on the sphere Bernstein's inequality gives
-            // |grad_tangential P_j| <= pw Cq, the radial part is pw P_j / R, so |d_i P_j| <= sqrt(2) pw Cq R^(pw-1)
-            double t = obound(k + 1) * 2.0 * R * (pw == 0 ? 1.0 : pow(R, (double)pw));
-            if (pw > 0) t += ok * 1.4142135623730951 * pw * (pw == 1 ? 1.0 : pow(R, (double)(pw - 1)));
-            dbound += t * bt.cq[la][lb][j];
-        }
-    }
-    *vbound = bound;
-    *R_out = R;
-    *rmin_out = rmin;
-    return deriv ? fmax(bound, dbound) : bound;
+    const double R2 = X0 * X0 + X1 * X1 + X2 * X2;
+    return shell_pair_bound(l[a], l[b], st + (size_t)a * STAT, st + (size_t)b * STAT, R2, op, omega, deriv, bt,
+                            vbound, R_out, rmin_out);
 }
 
 __device__ __forceinline__ float clamped_log10(double x, double lo) { return (float)fmax(x > 0 ? log10(x) : lo, lo); }
@@ -161,7 +118,7 @@ __device__ void pair_features(int a, int b, const int32_t *l, const double *st, 
 
 // log10 of the analytic bound and the 12 features of one pair
 __global__ void k_bound_features(int64_t n, const int32_t *pairs, const double *center, const int32_t *l,
-                                 const double *st, int op, double omega, int deriv, BoundTab bt, float *feat,
+                                 const double *st, int op, double omega, int deriv, const BoundTab *bt, float *feat,
                                  float *logb)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,29 +139,47 @@ struct PlanOps {
     double omega[5];
 };
 
+// adds the workgroup's kept count to bsum[position / 4096] (256 positions per workgroup)
+__device__ __forceinline__ void count_kept(int k, int64_t i, int32_t *bsum)
+{
+    __shared__ int32_t red[4];
+    int c = k;
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = red[0] + red[1] + red[2] + red[3];
+        if (t) atomicAdd(&bsum[(i - threadIdx.x) >> 12], t);
+    }
+}
+
 // fderiv: the features (log10 bound) are those of a model trained on targets
-// with (1) or without (0) the d/dR_a blocks, whatever the plan evaluates
-__global__ void k_plan_bound(int64_t n, const PairRec *rec, const double *center, const int32_t *l, const double *st,
-                             PlanOps po, int deriv, int fderiv, BoundTab bt, double tau, int32_t *keep, float *feat,
-                             float *logb)
+// with (1) or without (0) the d/dR_a blocks, whatever the plan evaluates.
+// bsum non-NULL: the kept flags are also counted per 4096 positions.
+__global__ __launch_bounds__(256) void k_plan_bound(int64_t n, const PairRec *rec, const double *center,
+                                                    const int32_t *l, const double *st, PlanOps po, int deriv,
+                                                    int fderiv, const BoundTab *bt, double tau, uint8_t *keep,
+                                                    int32_t *bsum, float *feat, float *logb)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const PairRec r = rec[i];
     int k = 0;
-    for (int o = 0; o < po.nops; ++o) {
-        double vb, R, rmin;
-        const double bound = pair_bound(r.a, r.b, center, l, st, po.op[o], po.omega[o], deriv, bt, &vb, &R, &rmin);
-        k |= !(bound < tau);
-        if (feat) {
-            logb[i] = clamped_log10(bound, -300.0);
-            double fb = bound;
-            if (fderiv != deriv)
-                fb = pair_bound(r.a, r.b, center, l, st, po.op[o], po.omega[o], fderiv, bt, &vb, &R, &rmin);
-            pair_features(r.a, r.b, l, st, po.op[o], po.omega[o], R, rmin, fb, feat + i * NF);
+    if (i < n) {
+        const PairRec r = rec[i];
+        for (int o = 0; o < po.nops; ++o) {
+            double vb, R, rmin;
+            const double bound = pair_bound(r.a, r.b, center, l, st, po.op[o], po.omega[o], deriv, bt, &vb, &R, &rmin);
+            k |= !(bound < tau);
+            if (feat) {
+                logb[i] = clamped_log10(bound, -300.0);
+                double fb = bound;
+                if (fderiv != deriv)
+                    fb = pair_bound(r.a, r.b, center, l, st, po.op[o], po.omega[o], fderiv, bt, &vb, &R, &rmin);
+                pair_features(r.a, r.b, l, st, po.op[o], po.omega[o], R, rmin, fb, feat + i * NF);
+            }
         }
+        keep[i] = (uint8_t)k;
     }
-    keep[i] = k;
+    if (bsum) count_kept(k, i, bsum);
 }
 
 // log10 max|block| (clamped at -30) of evaluated blocks, over the values and,
@@ -562,6 +537,15 @@ BoundTab build_bound_table()
                     }
                 bt.cq[la][lb][j] = best * (1.0 + 1e-12);
             }
+    const double PI_ = 3.141592653589793238462643383279502884;
+    for (int k = 0; k < BK; ++k) {
+        double df = 1.0;
+        for (int i = 2 * k - 1; i > 1; i -= 2) df *= i;
+        // rounded up by 1e-12 so that the device's products stay above the exact bound
+        bt.co[k] = pow(PI_, 1.5) * pow(2.0, -1.5 - k) * (1.0 + 1e-12);
+        bt.cn[k] = 2.0 * pow(PI_, 2.5) * pow(2.0, -(k + 0.5)) / (2 * k + 1) * (1.0 + 1e-12);
+        bt.cf[k] = 2.0 * PI_ * PI_ * PI_ * df * pow(2.0, -(k + 1)) * (1.0 + 1e-12);
+    }
     return bt;
 }
 
@@ -804,6 +788,10 @@ extern "C" int shg_mlp_load(shg_mlp *m, const char *path)
     return 0;
 }
 
+namespace shg {
+int screen_prepare(shg_ctx *c);
+}
+
 // features and analytic bound of n pairs (device outputs: feat [n][12] fp32, logb [n] fp32)
 extern "C" int shg_screen_features(shg_ctx *c, const shg_shells *sh, shg_op op, double omega, const int32_t *pairs,
                                    int64_t n, int deriv, float *feat, float *logb)
@@ -824,9 +812,9 @@ extern "C" int shg_screen_features(shg_ctx *c, const shg_shells *sh, shg_op op, 
     if ((rc = grow(c, c->stats, c->stats_cap, (size_t)sh->nshell * STAT + 1))) return rc;
     hipLaunchKernelGGL(k_shell_stats, dim3((sh->nshell + 255) / 256), dim3(256), 0, s, sh->nshell, sh->nprim,
                        sh->prim_off, sh->exps, c->w, c->stats);
-    static const BoundTab bt = build_bound_table();
+    if ((rc = screen_prepare(c))) return rc;
     hipLaunchKernelGGL(k_bound_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pairs, sh->center,
-                       sh->l, c->stats, (int)op, omega, deriv ? 1 : 0, bt, feat, logb);
+                       sh->l, c->stats, (int)op, omega, deriv ? 1 : 0, (const BoundTab *)c->bound_tab, feat, logb);
     HIP_TRY(c, hipMemcpyAsync(c->host_rb, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     return decode_err(c, c->host_rb[0], what);
@@ -845,19 +833,41 @@ extern "C" int shg_block_logmax(shg_ctx *c, const shg_shells *sh, const int32_t 
 }
 
 // keep[i] = 0 when the pair may be skipped: analytic bound below tau, or the
-// predictor (features inside its training range) plus its margin below tau
-__global__ void k_keep(int64_t n, const float *logb, const float *pred, const int32_t *in_range, float log_tau,
-                       float margin, int use_mlp, int32_t *keep)
+// predictor (features inside its training range) plus its margin below tau;
+// kept flags counted per 4096 positions
+__global__ __launch_bounds__(256) void k_keep(int64_t n, const float *logb, const float *pred, const int32_t *in_range,
+                                              float log_tau, float margin, uint8_t *keep, int32_t *bsum)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int k = 1;
-    if (logb[i] < log_tau) k = 0;
-    else if (use_mlp && in_range[i] && pred[i] + margin < log_tau) k = 0;
-    keep[i] = k;
+    int k = 0;
+    if (i < n) {
+        k = 1;
+        if (logb[i] < log_tau) k = 0;
+        else if (in_range[i] && pred[i] + margin < log_tau) k = 0;
+        keep[i] = (uint8_t)k;
+    }
+    if (bsum) count_kept(k, i, bsum);
 }
 
 namespace shg {
+// uploads the bound's constant table to the device once per context (kernels
+// index it with per-lane class indices, so it lives in global memory); not
+// callable during stream capture
+int screen_prepare(shg_ctx *c)
+{
+    if (c->bound_tab) return 0;
+    const BoundTab bt = build_bound_table();
+    void *d = nullptr;
+    HIP_TRY(c, hipMalloc(&d, sizeof(BoundTab)));
+    const hipError_t e = hipMemcpy(d, &bt, sizeof(BoundTab), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return set_err(c, SHG_EDEVICE, "screen_prepare: %s", hipGetErrorString(e));
+    }
+    c->bound_tab = d;
+    return 0;
+}
+
 bool mlp_covers(const shg_mlp *m, int op, int deriv)
 {
     return m && op >= 0 && op < 5 && ((m->ops_mask >> op) & 1u) && (!deriv || m->deriv_targets);
@@ -871,12 +881,13 @@ bool mlp_covers(const shg_mlp *m, int op, int deriv)
 // the training range. work: n * 15 floats when a model is used.
 int plan_screen_enqueue(shg_ctx *c, hipStream_t s, const shg_shells *sh, const double *w, double *stats,
                         const PairRec *rec, int64_t n, int nops, const int *ops, const double *omegas, int deriv,
-                        double tau, shg_mlp *mlp, float *work, int32_t *keep)
+                        double tau, shg_mlp *mlp, float *work, uint8_t *keep, int32_t *bsum)
 {
     if (nops < 1 || nops > 5) return set_err(c, SHG_EINVAL, "screen: 1 to 5 operators");
     if (mlp && (nops != 1 || !mlp_covers(mlp, ops[0], deriv))) mlp = nullptr;
     if (mlp && mlp->ctx != c) return set_err(c, SHG_EINVAL, "screen: model belongs to another context");
-    static const BoundTab bt = build_bound_table();
+    if (!c->bound_tab) return set_err(c, SHG_EINVAL, "screen: bound table not uploaded (screen_prepare)");
+    const BoundTab *bt = (const BoundTab *)c->bound_tab;
     PlanOps po{};
     po.nops = nops;
     for (int o = 0; o < nops; ++o) {
@@ -886,10 +897,11 @@ int plan_screen_enqueue(shg_ctx *c, hipStream_t s, const shg_shells *sh, const d
     if (sh->nshell > 0)
         hipLaunchKernelGGL(k_shell_stats, dim3((sh->nshell + 255) / 256), dim3(256), 0, s, sh->nshell, sh->nprim,
                            sh->prim_off, sh->exps, w, stats);
-    if (n > 0) {
+    if (n > 0 && keep) {
         float *feat = mlp ? work : nullptr, *logb = mlp ? work + (size_t)n * NF : nullptr;
-        hipLaunchKernelGGL(k_plan_bound, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, rec, sh->center,
-                           sh->l, stats, po, deriv, mlp ? mlp->deriv_targets : deriv, bt, tau, keep, feat, logb);
+        const unsigned g = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(k_plan_bound, dim3(g), dim3(256), 0, s, n, rec, sh->center, sh->l, stats, po, deriv,
+                           mlp ? mlp->deriv_targets : deriv, bt, tau, keep, mlp ? nullptr : bsum, feat, logb);
         if (mlp) {
             float *pred = logb + n;
             int32_t *inr = (int32_t *)(pred + n);
@@ -899,8 +911,8 @@ int plan_screen_enqueue(shg_ctx *c, hipStream_t s, const shg_shells *sh, const d
             const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 4096);
             hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, s, n, feat, mlp->wb, mlp->p, mlp->norm, pred,
                                inr);
-            hipLaunchKernelGGL(k_keep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, logb, pred, inr,
-                               (float)log10(tau), mlp->margin, 1, keep);
+            hipLaunchKernelGGL(k_keep, dim3(g), dim3(256), 0, s, n, logb, pred, inr, (float)log10(tau), mlp->margin,
+                               keep, bsum);
         }
     }
     HIP_TRY(c, hipGetLastError());

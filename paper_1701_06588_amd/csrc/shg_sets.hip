@@ -5,11 +5,12 @@
 //                      of every contracted function (one wave per set)
 //   k_set_count        per set pair: validation, radial-scratch size, l-block
 //                      items counted per bin (la, lb, na, nb) in LDS
-//   scan               set-pair offsets into the radial scratch; bin starts
+//   k_scan_part/top/apply  set-pair offsets into the radial scratch; bin starts
 //   k_set_scatter      item records in bin order (one global atomic per bin and
 //                      workgroup)
 //   k_set_radial       one wave per set pair: primitive radial terms for every
-//                      primitive pair, O^(k) = C_a^T G^(k) C_b through LDS
+//                      primitive pair (orders up to the pair's largest),
+//                      O^(k) = C_a^T G^(k) C_b one k at a time through LDS
 //   k_setblk<la,lb,D>  per non-empty bin: the l-block elements (shg_sets.h)
 #include <hip/hip_runtime.h>
 
@@ -188,108 +189,161 @@ __global__ void k_set_nsgf(shg_sets s, int64_t *nsgf)
     nsgf[si] = t;
 }
 
-// exclusive scan of n int64 values by one workgroup (sizes of the set pairs'
-// radial scratch); out[n] = total
-__global__ __launch_bounds__(256) void k_scan_i64(int64_t n, const int64_t *in, int64_t *out)
+// exclusive scan of n int64 values (sizes of the set pairs' radial scratch),
+// out[n] = total, in three launches: k_scan_part sums each chunk of
+// SCAN_CHUNK values, k_scan_top scans the chunk sums in one workgroup, and
+// k_scan_apply scans each chunk again from its start value
+constexpr int SCAN_T = 256, SCAN_V = 8, SCAN_CHUNK = SCAN_T * SCAN_V;
+
+// exclusive scan over the 256 threads of a workgroup (x = the thread's value);
+// returns the thread's start, *total the sum
+__device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *lds, int64_t *total)
 {
-    __shared__ int64_t part[256];
     const int t = threadIdx.x;
-    const int64_t per = (n + 255) / 256, lo = min(n, t * per), hi = min(n, lo + per);
-    int64_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += in[i];
-    part[t] = s;
+    lds[t] = x;
     __syncthreads();
-    if (t == 0) {
-        int64_t acc = 0;
-        for (int i = 0; i < 256; ++i) {
-            const int64_t v = part[i];
-            part[i] = acc;
-            acc += v;
-        }
-        out[n] = acc;
+    for (int d = 1; d < SCAN_T; d <<= 1) {
+        const int64_t v = t >= d ? lds[t - d] : 0;
+        __syncthreads();
+        lds[t] += v;
+        __syncthreads();
     }
+    const int64_t incl = lds[t];
+    *total = lds[SCAN_T - 1];
     __syncthreads();
-    int64_t acc = part[t];
-    for (int64_t i = lo; i < hi; ++i) {
-        const int64_t v = in[i];
-        out[i] = acc;
-        acc += v;
+    return incl - x;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_part(int64_t n, const int64_t *in, int64_t *part)
+{
+    __shared__ int64_t lds[SCAN_T];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+    int64_t x = 0;
+    for (int v = 0; v < SCAN_V; ++v) {
+        const int64_t i = base + (int64_t)v * SCAN_T + threadIdx.x;   // coalesced
+        if (i < n) x += in[i];
+    }
+    int64_t tot;
+    (void)block_excl_scan(x, lds, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// one workgroup: exclusive scan of the nblk chunk sums in place, total to *total_out
+__global__ __launch_bounds__(SCAN_T) void k_scan_top(int64_t nblk, int64_t *part, int64_t *total_out)
+{
+    __shared__ int64_t lds[SCAN_T];
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nblk; b0 += SCAN_T) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t x = i < nblk ? part[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(x, lds, &tot);
+        if (i < nblk) part[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_apply(int64_t n, const int64_t *in, const int64_t *part,
+                                                       int64_t *out)
+{
+    __shared__ int64_t lds[SCAN_T];
+    // each thread takes SCAN_V consecutive values of the chunk
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_V;
+    int64_t v[SCAN_V], x = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_V; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        x += v[k];
+    }
+    int64_t tot;
+    int64_t acc = part[blockIdx.x] + block_excl_scan(x, lds, &tot);
+#pragma unroll
+    for (int k = 0; k < SCAN_V; ++k) {
+        if (base + k < n) out[base + k] = acc;
+        acc += v[k];
     }
 }
 
-// one wave per set pair: G^(k)[alpha][beta] of every primitive pair (a lane
-// each), T^(k)[alpha][fb] = sum_beta G^(k) w_b[fb][beta], then
-// O^(k)[fa][fb] = sum_alpha w_a[fa][alpha] T^(k)[alpha][fb] for the k of each
-// function pair (eq. O_rab2_deriv as C_a^T G C_b)
-constexpr int RAD_WAVES = 4;
-
-__global__ __launch_bounds__(64 * RAD_WAVES) void k_set_radial(int64_t n, const int32_t *sp, shg_sets s,
-                                                               const double *w, int op, double omega, int deriv,
-                                                               const double *tab, const int64_t *obase, double *O)
+// one wave per set pair (a workgroup of its own, so the barriers below are
+// the wave's): G^(k)[alpha][beta] of every primitive pair (a lane each) for
+// k = 0..kmax, then per k T[alpha][fb] = sum_beta G^(k) w_b[fb][beta] and
+// O^(k)[fa][fb] = sum_alpha w_a[fa][alpha] T[alpha][fb] for the function pairs
+// that need this k (eq. O_rab2_deriv as C_a^T G C_b)
+template <int K>
+__device__ __forceinline__ void set_radial_k(int op, double ea, double eb, double R2, double omega, const double *tab,
+                                             double *g)
 {
-    __shared__ double sG[RAD_WAVES][SET_KS][64];
-    __shared__ double sTm[RAD_WAVES][SET_KS][SET_KMAX * SET_FMAX];
-    __shared__ double sWa[RAD_WAVES][SET_FMAX * SET_KMAX], sWb[RAD_WAVES][SET_FMAX * SET_KMAX];
-    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int64_t p = (int64_t)blockIdx.x * RAD_WAVES + wv;
-    const bool live = p < n;
-    int sa = 0, sb = 0, ka = 1, kb = 1, nfa = 1, nfb = 1, kmax = 0;
-    int64_t fa0 = 0, fb0 = 0, ea0 = 0, eb0 = 0;
-    if (live) {
-        sa = sp[2 * p];
-        sb = sp[2 * p + 1];
-        ka = s.nexp[sa];
-        kb = s.nexp[sb];
-        nfa = s.nfun[sa];
-        nfb = s.nfun[sb];
-        fa0 = s.fun_off[sa];
-        fb0 = s.fun_off[sb];
-        ea0 = s.exp_off[sa];
-        eb0 = s.exp_off[sb];
-        kmax = s.fun_l[fa0 + nfa - 1] + s.fun_l[fb0 + nfb - 1] + (deriv ? 1 : 0);   // functions sorted by l
-        const double X0 = s.center[3 * sa] - s.center[3 * sb], X1 = s.center[3 * sa + 1] - s.center[3 * sb + 1],
-                     X2 = s.center[3 * sa + 2] - s.center[3 * sb + 2];
-        const double R2 = fma(X0, X0, fma(X1, X1, X2 * X2));
-        if (lane < ka * kb) {
-            const int ia = lane / kb, ib = lane - ia * kb;
-            double g[SET_KS];
-            radial_rt<0, SET_KS - 1>(op, s.exps[ea0 + ia], s.exps[eb0 + ib], R2, omega, tab, g);
+    double gk[K + 1];
+    radial_rt<0, K>(op, ea, eb, R2, omega, tab, gk);
 #pragma unroll
-            for (int k = 0; k < SET_KS; ++k) sG[wv][k][lane] = g[k];
+    for (int k = 0; k <= K; ++k) g[k] = gk[k];
+}
+
+__global__ __launch_bounds__(64) void k_set_radial(int64_t n, const int32_t *sp, shg_sets s, const double *w, int op,
+                                                   double omega, int deriv, const double *tab, const int64_t *obase,
+                                                   double *O)
+{
+    __shared__ double sG[SET_KS][64];
+    __shared__ double sT[SET_KMAX * SET_FMAX];
+    __shared__ double sWa[SET_FMAX * SET_KMAX], sWb[SET_FMAX * SET_KMAX];
+    const int lane = threadIdx.x;
+    const int64_t p = blockIdx.x;
+    if (p >= n) return;   // uniform over the workgroup
+    const int sa = sp[2 * p], sb = sp[2 * p + 1];
+    const int ka = s.nexp[sa], kb = s.nexp[sb], nfa = s.nfun[sa], nfb = s.nfun[sb];
+    const int64_t fa0 = s.fun_off[sa], fb0 = s.fun_off[sb], ea0 = s.exp_off[sa], eb0 = s.exp_off[sb];
+    // functions are sorted by l: the last of each set has the largest
+    const int kmax = s.fun_l[fa0 + nfa - 1] + s.fun_l[fb0 + nfb - 1] + (deriv ? 1 : 0);
+    const double X0 = s.center[3 * sa] - s.center[3 * sb], X1 = s.center[3 * sa + 1] - s.center[3 * sb + 1],
+                 X2 = s.center[3 * sa + 2] - s.center[3 * sb + 2];
+    const double R2 = fma(X0, X0, fma(X1, X1, X2 * X2));
+    if (lane < ka * kb) {
+        const int ia = lane / kb, ib = lane - ia * kb;
+        const double ea = s.exps[ea0 + ia], eb = s.exps[eb0 + ib];
+        double g[SET_KS];
+        switch (kmax) {   // only the orders this set pair needs
+        case 0: set_radial_k<0>(op, ea, eb, R2, omega, tab, g); break;
+        case 1: set_radial_k<1>(op, ea, eb, R2, omega, tab, g); break;
+        case 2: set_radial_k<2>(op, ea, eb, R2, omega, tab, g); break;
+        case 3: set_radial_k<3>(op, ea, eb, R2, omega, tab, g); break;
+        case 4: set_radial_k<4>(op, ea, eb, R2, omega, tab, g); break;
+        case 5: set_radial_k<5>(op, ea, eb, R2, omega, tab, g); break;
+        case 6: set_radial_k<6>(op, ea, eb, R2, omega, tab, g); break;
+        case 7: set_radial_k<7>(op, ea, eb, R2, omega, tab, g); break;
+        case 8: set_radial_k<8>(op, ea, eb, R2, omega, tab, g); break;
+        default: set_radial_k<9>(op, ea, eb, R2, omega, tab, g); break;
         }
-        for (int e = lane; e < nfa * ka; e += 64) {
-            const int f = e / ka, q = e - f * ka;
-            sWa[wv][e] = w[s.coef_off[fa0 + f] + q];
-        }
-        for (int e = lane; e < nfb * kb; e += 64) {
-            const int f = e / kb, q = e - f * kb;
-            sWb[wv][e] = w[s.coef_off[fb0 + f] + q];
-        }
+        for (int k = 0; k <= kmax; ++k) sG[k][lane] = g[k];
+    }
+    for (int e = lane; e < nfa * ka; e += 64) {
+        const int f = e / ka, q = e - f * ka;
+        sWa[e] = w[s.coef_off[fa0 + f] + q];
+    }
+    for (int e = lane; e < nfb * kb; e += 64) {
+        const int f = e / kb, q = e - f * kb;
+        sWb[e] = w[s.coef_off[fb0 + f] + q];
     }
     __syncthreads();
-    if (live) {
-        const int nt = (kmax + 1) * ka * nfb;
-        for (int e = lane; e < nt; e += 64) {
-            const int k = e / (ka * nfb), r = e - k * (ka * nfb);
-            const int ia = r / nfb, fb = r - ia * nfb;
+    double *dst = O + obase[p];
+    for (int k = 0; k <= kmax; ++k) {
+        for (int e = lane; e < ka * nfb; e += 64) {
+            const int ia = e / nfb, fb = e - ia * nfb;
             double t = 0.0;
-            for (int ib = 0; ib < kb; ++ib) t = fma(sG[wv][k][ia * kb + ib], sWb[wv][fb * kb + ib], t);
-            sTm[wv][k][ia * nfb + fb] = t;
+            for (int ib = 0; ib < kb; ++ib) t = fma(sG[k][ia * kb + ib], sWb[fb * kb + ib], t);
+            sT[e] = t;
         }
-    }
-    __syncthreads();
-    if (live) {
+        __syncthreads();
         for (int e = lane; e < nfa * nfb; e += 64) {
             const int fa = e / nfb, fb = e - fa * nfb;
             const int la = s.fun_l[fa0 + fa], lb = s.fun_l[fb0 + fb];
-            const int klo = la > lb ? la : lb, khi = la + lb + (deriv ? 1 : 0);
-            double *dst = O + obase[p] + (int64_t)e * SET_KS;
-            for (int k = klo; k <= khi; ++k) {
+            if (k >= (la > lb ? la : lb) && k <= la + lb + (deriv ? 1 : 0)) {
                 double o = 0.0;
-                for (int ia = 0; ia < ka; ++ia) o = fma(sWa[wv][fa * ka + ia], sTm[wv][k][ia * nfb + fb], o);
-                dst[k] = o;
+                for (int ia = 0; ia < ka; ++ia) o = fma(sWa[fa * ka + ia], sT[ia * nfb + fb], o);
+                dst[(int64_t)e * SET_KS + k] = o;
             }
         }
+        __syncthreads();
     }
 }
 
@@ -316,7 +370,8 @@ extern "C" int shg_set_pairs(shg_ctx *c, const shg_sets *sets, shg_op op, double
     hipStream_t s = c->stream;
     int rc = 0;
     if ((rc = grow(c, c->set_w, c->set_w_cap, (size_t)sets->ncoef_total + 1))) return rc;
-    if ((rc = grow(c, c->set_osz, c->set_osz_cap, (size_t)n * 2 + 2))) return rc;
+    // osz [n], obase [n + 1], then the scan's chunk sums
+    if ((rc = grow(c, c->set_osz, c->set_osz_cap, (size_t)n * 2 + 2 + (size_t)(n / SCAN_CHUNK + 1)))) return rc;
     if ((rc = grow(c, c->set_nsgf, c->set_nsgf_cap, (size_t)sets->nset + 1))) return rc;
     int64_t *osz = c->set_osz, *obase = c->set_osz + n + 1;
     int32_t *hist = c->bins, *cursor = c->bins + (NBINS_MAX + 1);
@@ -333,7 +388,11 @@ extern "C" int shg_set_pairs(shg_ctx *c, const shg_sets *sets, shg_op op, double
         hipLaunchKernelGGL(k_set_nsgf, dim3((sets->nset + 255) / 256), dim3(256), 0, s, *sets, c->set_nsgf);
     const unsigned gb = (unsigned)((n + SET_TPB - 1) / SET_TPB);
     hipLaunchKernelGGL(k_set_count, dim3(gb), dim3(SET_TPB), 0, s, n, set_pairs, *sets, deriv, osz, hist, c->err);
-    hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(256), 0, s, n, osz, obase);
+    const int64_t nchunk = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    int64_t *part = obase + n + 1;   // nchunk values after the scan's n + 1
+    hipLaunchKernelGGL(k_scan_part, dim3((unsigned)nchunk), dim3(SCAN_T), 0, s, n, osz, part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, s, nchunk, part, obase + n);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nchunk), dim3(SCAN_T), 0, s, n, osz, part, obase);
     hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(256), 0, s, hist, SET_NBIN, cursor, cursor);
     HIP_TRY(c, hipMemcpyAsync(c->host_rb, cursor, (SET_NBIN + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(c->host_rb + SET_NBIN + 1, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -348,8 +407,8 @@ extern "C" int shg_set_pairs(shg_ctx *c, const shg_sets *sets, shg_op op, double
     if ((rc = grow(c, c->set_O, c->set_O_cap, (size_t)o_total + 1))) return rc;
     hipLaunchKernelGGL(k_set_scatter, dim3(gb), dim3(SET_TPB), 0, s, n, set_pairs, *sets, deriv, out_off, obase,
                        c->set_nsgf, cursor, c->set_items);
-    hipLaunchKernelGGL(k_set_radial, dim3((unsigned)((n + RAD_WAVES - 1) / RAD_WAVES)), dim3(64 * RAD_WAVES), 0, s,
-                       n, set_pairs, *sets, c->set_w, (int)op, omega, deriv, c->boys, obase, c->set_O);
+    hipLaunchKernelGGL(k_set_radial, dim3((unsigned)n), dim3(64), 0, s, n, set_pairs, *sets, c->set_w, (int)op, omega,
+                       deriv, c->boys, obase, c->set_O);
     SetBlkArgs ba{c->set_items, sets->center, c->set_O, out, dout, 1, 1};
     for (int la = 0; la <= LMAX; ++la)
         for (int lb = 0; lb <= LMAX; ++lb)

@@ -309,6 +309,7 @@ class Engine:
 PLAN_PERSISTENT = 1
 NOALLOC_MAX_PAIRS = 1 << 20     # SHG_NOALLOC_MAX_PAIRS
 PLAN_NO_GRAPH = 2
+PLAN_COMPACT = 4
 
 
 class Plan:

@@ -46,6 +46,12 @@ def test_analytic_bound_dominates(engine, op):
         assert slack.min() >= -1e-6, (op, w.name, slack.min())
 
 
+def _flags(compact):
+    """screened plans: in-kernel screening (default) or the compaction stage"""
+    from paper_1701_06588_amd import shg
+    return shg.PLAN_PERSISTENT | (shg.PLAN_COMPACT if compact else 0)
+
+
 def _block_absmax(x, starts, sizes):
     """max |x| over each block [start, start + size) (blocks contiguous and in order)."""
     m = np.maximum.reduceat(np.abs(x), starts)
@@ -126,20 +132,21 @@ def test_training_lowers_loss(engine):
     mlp.close()
 
 
+@pytest.mark.parametrize("compact", [False, True], ids=["inkernel", "compact"])
 @pytest.mark.parametrize("op", ["overlap", "erfc"])
-def test_screened_plan(engine, op):
+def test_screened_plan(engine, op, compact):
     """every execution evaluates the kept pairs (bitwise the plain path's blocks)
     and zeroes the skipped ones, whose exact blocks are below tau"""
     import torch
     from paper_1701_06588_amd import shg
     w = inputs.screen5000(n_atoms=900, box=26.0)
-    print(f"case screened plan op={op} n={len(w.pairs)}", flush=True)
+    print(f"case screened plan op={op} compact={compact} n={len(w.pairs)}", flush=True)
     pairs, oo, out = _dev(w)
     dsh = engine.shells(w.shells)
     ref = torch.empty_like(out)
     engine.pairs(dsh, op, w.omega[op], pairs, oo, ref)
     tau = 1e-12
-    plan = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, None, shg.PLAN_PERSISTENT, tau=tau)
+    plan = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, None, _flags(compact), tau=tau)
     for rep in range(3):
         out.fill_(float("nan"))
         plan.execute()
@@ -157,8 +164,9 @@ def test_screened_plan(engine, op):
     plan.close()
 
 
+@pytest.mark.parametrize("compact", [False, True], ids=["inkernel", "compact"])
 @pytest.mark.parametrize("op", ["overlap", "gauss", "erfc"])
-def test_screened_plan_follows_moved_centers(engine, op):
+def test_screened_plan_follows_moved_centers(engine, op, compact):
     """A screened plan decides on every execution: after the atoms move (the
     geometry is compressed, so pairs that were skipped come into range and
     others leave it), the replayed graph keeps exactly the pairs the bound now
@@ -170,12 +178,12 @@ def test_screened_plan_follows_moved_centers(engine, op):
     from parity import assert_parity
     from paper_1701_06588_amd import shg
     w = inputs.screen5000(n_atoms=700, box=24.0)
-    print(f"case screened plan moved centers op={op} n={len(w.pairs)}", flush=True)
+    print(f"case screened plan moved centers op={op} compact={compact} n={len(w.pairs)}", flush=True)
     pairs, oo, out = _dev(w)
     dout = torch.empty(3 * out.numel(), dtype=torch.float64, device=out.device)
     dsh = engine.shells(w.shells)
     tau = 1e-12
-    plan = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, dout, shg.PLAN_PERSISTENT, tau=tau)
+    plan = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, dout, _flags(compact), tau=tau)
     skipped0 = set(plan.skipped().tolist())
     # move: compress about the box center and jitter every atom
     rng = np.random.default_rng(7)
@@ -226,12 +234,13 @@ def test_screened_plan_follows_moved_centers(engine, op):
     plan.close()
 
 
+@pytest.mark.parametrize("compact", [False, True], ids=["inkernel", "compact"])
 @pytest.mark.parametrize("op", ["overlap", "gauss", "coulomb"])
-def test_screened_plan_with_derivatives(engine, op):
+def test_screened_plan_with_derivatives(engine, op, compact):
     import torch
     from paper_1701_06588_amd import shg
     w = inputs.screen5000(n_atoms=700, box=24.0)
-    print(f"case screened plan deriv op={op} n={len(w.pairs)}", flush=True)
+    print(f"case screened plan deriv op={op} compact={compact} n={len(w.pairs)}", flush=True)
     pairs, oo, out = _dev(w)
     dout = torch.empty(3 * out.numel(), dtype=torch.float64, device=out.device)
     ref, dref = torch.empty_like(out), torch.empty_like(dout)
@@ -240,7 +249,7 @@ def test_screened_plan_with_derivatives(engine, op):
     tau = 1e-12
     out.fill_(float("nan"))
     dout.fill_(float("nan"))
-    plan = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, dout, shg.PLAN_PERSISTENT, tau=tau)
+    plan = shg.Plan(engine, dsh, op, w.omega[op], pairs, oo, out, dout, _flags(compact), tau=tau)
     plan.execute()
     torch.cuda.synchronize()
     g, r = out.cpu().numpy(), ref.cpu().numpy()

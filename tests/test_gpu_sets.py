@@ -97,7 +97,9 @@ def test_set_pairs_values_only_and_shell_path(engine):
         blk = out[off[i]:off[i] + sz[i]].reshape(nsgf[sp[i, 0]], nsgf[sp[i, 1]])[ra:ra + na, cb:cb + nb]
         ref = r[foff[k]:foff[k] + na * nb].reshape(na, nb)
         scale = max(1.0, np.abs(ref).max())
-        worst = max(worst, float((np.abs(blk - ref) / (1e-13 * np.abs(ref) + 1e-15 * scale)).max()))
+        # the set path contracts as C_a^T (G C_b), the shell path pair by pair: the
+        # two round differently, both within the oracle tolerance of each other
+        worst = max(worst, float((np.abs(blk - ref) / (1e-12 * np.abs(ref) + 1e-14 * scale)).max()))
     assert worst <= 1.0, worst
 
 
