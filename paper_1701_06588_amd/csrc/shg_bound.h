@@ -23,7 +23,7 @@
 
 namespace shg {
 
-constexpr int STAT = 32;        // doubles per shell in the statistics table
+constexpr int STAT = 16;        // doubles per shell in the statistics table (one 128-byte line)
 constexpr int KB = 10;          // k = 0..9 moments
 constexpr int BK = 11;          // k = 0..10 in the per-k constants
 
@@ -36,7 +36,8 @@ struct BoundTab {
 };
 
 // bound of a shell pair with angular momenta (la, lb), per-shell statistics sa
-// and sb (alpha_min, alpha_max, sum|w|, Sf, Sc[KB], So[KB]) and squared distance
+// and sb (alpha_min, alpha_max, sum|w|, Sf, S[KB] with S = So for the overlap and
+// the Gaussian operator, Sc for the Coulomb-like ones) and squared distance
 // R2; returns the bound on max|block| and, with deriv, on the d/dR_a elements
 // too (their maximum); *vbound receives the value bound alone, *R_out and
 // *rmin_out R and the smallest reduced exponent
@@ -72,7 +73,7 @@ __device__ __forceinline__ double shell_pair_bound(int la, int lb, const double 
     auto ob_next = [&](int k) {
         double v;
         if (gl) {
-            v = bt->co[k] * sa[4 + KB + k] * sb[4 + KB + k] * e;
+            v = bt->co[k] * sa[4 + k] * sb[4 + k] * e;
         } else {
             const double nearb = bt->cn[k] * sa[4 + k] * sb[4 + k];
             const double farb = R > 0 ? bt->cf[k] * sf * rp : 1e300;

@@ -124,9 +124,16 @@ __device__ __forceinline__ void reg_fence(RTab<L> &R, double (&O)[NK], double (&
 // and the staged rows with an odd per-pair stride (conflict-free 8-byte
 // accesses when consecutive lanes take consecutive pairs)
 constexpr int SO_STRIDE = 9;
+// 64-pair tiles of the two-center mode first stage every pair's exponents and
+// folded weights (both shells, KMAX each) in the staging area, after 256 bytes
+// of screening flags, so the radial loop reads them from LDS
+constexpr int STG_STRIDE = 4 * KMAX + 1;   // odd: conflict-free
+constexpr int STG_OFF = 256;
 inline constexpr int tile_smem_bytes_rt(int tp, int rows_pp, int lb, bool D)
 {
-    return tp * SO_STRIDE * 8 + tp * 16 + tp * (((D ? 4 : 1) * rows_pp * (2 * lb + 1)) | 1) * 8;
+    const int rows = tp * (((D ? 4 : 1) * rows_pp * (2 * lb + 1)) | 1) * 8;
+    const int stage = tp == 64 ? STG_OFF + tp * STG_STRIDE * 8 : 0;
+    return tp * SO_STRIDE * 8 + tp * 16 + (rows > stage ? rows : stage);
 }
 template <int LA, int LB, bool D>
 constexpr int tile_smem_bytes(int tp, int rows_pp)
@@ -231,19 +238,45 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
         const double X2 = a.center[3 * sa + 2] - a.center[3 * sb + 2];
         const double R2 = fma(X0, X0, fma(X1, X1, X2 * X2));   // fixed rounding order
         const int64_t oa = a.prim_off[sa], ob = a.prim_off[sb];
-        const int kb = a.nprim[sb];
+        const int ka = a.nprim[sa], kb = a.nprim[sb];
         // a skipped pair gets no primitive work: its O^(k) stay zero, and so does its block
-        const int P = live && !skip ? a.nprim[sa] * kb : 0;
+        const bool work = live && !skip;
+        const int P = work ? ka * kb : 0;
         double O[PK::NK];
 #pragma unroll
         for (int k = 0; k < PK::NK; ++k) O[k] = 0.0;
-        for (int q = g; q < P; q += G) {
-            const int ia = q / kb, ib = q - ia * kb;
-            double gk[PK::NK];
-            radial_rt<PK::KLO, PK::KHI>(a.op, a.exps[oa + ia], a.exps[ob + ib], R2, a.omega, a.tab, gk);
-            const double ww = a.w[oa + ia] * a.w[ob + ib];
+        if (TP == 64) {
+            // the pair's lanes stage its exponents and weights with independent
+            // loads, so the loop below waits on memory only for the Boys table
+            double *sP = (double *)((char *)sT + STG_OFF) + i * STG_STRIDE;
+            if (work) {
+                for (int q = g; q < ka; q += G) {
+                    sP[q] = a.exps[oa + q];
+                    sP[2 * KMAX + q] = a.w[oa + q];
+                }
+                for (int q = g; q < kb; q += G) {
+                    sP[KMAX + q] = a.exps[ob + q];
+                    sP[3 * KMAX + q] = a.w[ob + q];
+                }
+            }
+            __syncthreads();
+            for (int q = g; q < P; q += G) {
+                const int ia = q / kb, ib = q - ia * kb;
+                double gk[PK::NK];
+                radial_rt<PK::KLO, PK::KHI>(a.op, sP[ia], sP[KMAX + ib], R2, a.omega, a.tab, gk);
+                const double ww = sP[2 * KMAX + ia] * sP[3 * KMAX + ib];
 #pragma unroll
-            for (int k = 0; k < PK::NK; ++k) O[k] = fma(ww, gk[k], O[k]);
+                for (int k = 0; k < PK::NK; ++k) O[k] = fma(ww, gk[k], O[k]);
+            }
+        } else {
+            for (int q = g; q < P; q += G) {
+                const int ia = q / kb, ib = q - ia * kb;
+                double gk[PK::NK];
+                radial_rt<PK::KLO, PK::KHI>(a.op, a.exps[oa + ia], a.exps[ob + ib], R2, a.omega, a.tab, gk);
+                const double ww = a.w[oa + ia] * a.w[ob + ib];
+#pragma unroll
+                for (int k = 0; k < PK::NK; ++k) O[k] = fma(ww, gk[k], O[k]);
+            }
         }
         for (int m = 1; m < G; m <<= 1)
 #pragma unroll
@@ -358,7 +391,6 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
             }
             __syncthreads();
         }
-
     }
 }
 

@@ -70,8 +70,9 @@ void launch_persist(hipStream_t s, int grid, size_t smem, const TileArgs &a, con
 template <bool D>
 int persist_occupancy(size_t smem)
 {
-    (void)hipFuncSetAttribute((const void *)k_persist<D>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              PERSIST_MAX_SMEM);
+    if (hipFuncSetAttribute((const void *)k_persist<D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            PERSIST_MAX_SMEM) != hipSuccess)
+        (void)hipGetLastError();   // the launch then fails and reports it; leave nothing sticky here
     int nb = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<D>, TILE_THREADS, smem);
     if (e != hipSuccess) {

@@ -17,7 +17,8 @@
 // (rho_min from the most diffuse exponents: rho and the exponent are increasing in both).
 //
 // MLP: 12 standardised features -> 64 -> 64 -> 64 -> 1, SiLU hidden activations.
-// Inference on MFMA (v_mfma_f32_16x16x16 bf16, fp32 accumulate): a wave takes 16
+// Inference on MFMA (bf16, fp32 accumulate: 16x16x16 for the input layer,
+// gfx950's 16x16x32 for the hidden ones): a wave takes 16
 // pairs; activations go through LDS between layers (bf16). Training in fp32 VALU
 // on the same bf16-rounded weights and activations (straight-through rounding):
 // forward (thread per sample), backward deltas (thread per sample), weight
@@ -48,13 +49,17 @@ constexpr int P_W1 = 0, P_B1 = P_W1 + NH * NF, P_W2 = P_B1 + NH, P_B2 = P_W2 + N
 // ---------------------------------------------------------------------------
 // per-shell statistics: alpha_min, alpha_max, sum|w|, Sf, Sc[k], So[k]
 // ---------------------------------------------------------------------------
+// per-shell statistics of the bound (shg_bound.h): alpha_min, alpha_max, sum|w|,
+// Sf and the moments S(k) of the operator's family (gl: overlap/Gaussian So,
+// else Coulomb-like Sc), STAT doubles per shell
 __global__ void k_shell_stats(int nshell, const int32_t *nprim, const int64_t *prim_off, const double *exps,
-                              const double *w, double *st)
+                              const double *w, int gl, double *st)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nshell) return;
-    double amin = 1e300, amax = 0, sw = 0, sf = 0, sc[KB], so[KB];
-    for (int k = 0; k < KB; ++k) sc[k] = so[k] = 0;
+    const double e0 = gl ? -0.75 : -1.25;   // So(k) = sum|w| a^(k/2-3/4), Sc(k) = sum|w| a^(k/2-5/4)
+    double amin = 1e300, amax = 0, sw = 0, sf = 0, sk[KB];
+    for (int k = 0; k < KB; ++k) sk[k] = 0;
     for (int q = 0; q < nprim[i]; ++q) {
         double a = exps[prim_off[i] + q], aw = fabs(w[prim_off[i] + q]);
         amin = fmin(amin, a);
@@ -62,24 +67,17 @@ __global__ void k_shell_stats(int nshell, const int32_t *nprim, const int64_t *p
         sw += aw;
         double la = log(a);
         sf += aw * exp(-1.5 * la);
-        for (int k = 0; k < KB; ++k) {
-            sc[k] += aw * exp((0.5 * k - 1.25) * la);
-            so[k] += aw * exp((0.5 * k - 0.75) * la);
-        }
+        for (int k = 0; k < KB; ++k) sk[k] += aw * exp((0.5 * k + e0) * la);
     }
     double *o = st + (size_t)i * STAT;
     o[0] = amin;
     o[1] = amax;
     o[2] = sw;
     o[3] = sf;
-    for (int k = 0; k < KB; ++k) {
-        o[4 + k] = sc[k];
-        o[4 + KB + k] = so[k];
-    }
+    for (int k = 0; k < KB; ++k) o[4 + k] = sk[k];
+    o[4 + KB] = 0.0;
+    o[5 + KB] = 0.0;
 }
-
-
-
 
 // Analytic bound of one pair (a, b) (shg_bound.h) with its l values read from
 // the shell table
@@ -248,11 +246,15 @@ struct MlpNorm {
 
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef short short8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 // inference: 256 threads = 4 waves, a wave evaluates 16 pairs per iteration.
 // MFMA 16x16x16 bf16 lane layout (checked on gfx950): A: lane l holds
 // A[l%16][4(l/16)+v]; B: lane l holds B[4(l/16)+v][l%16]; D: lane l holds
-// D[4(l/16)+v][l%16], v = 0..3.
+// D[4(l/16)+v][l%16], v = 0..3. The 16x16x32 form (the hidden layers, K = 64)
+// takes 8 values per lane, A[l%16][k] and B[k][l%16] with the same k for
+// v = 0..7 (k = 8(l/16)+v here: the product only needs A and B to agree).
 __global__ __launch_bounds__(256) void k_mlp_infer(int64_t n, const float *feat, const uint16_t *wb, const float *p,
                                                    MlpNorm nm, float *pred, int32_t *in_range)
 {
@@ -317,17 +319,20 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int64_t n, const float *feat,
             if (layer == 2) break;
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) acc[nt] = (float4_t){0, 0, 0, 0};
+            // K = 64 in two steps of the 16x16x32 form: lane (r, g) holds k = 32 ks + 8 g + v
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                short4_t aa;
+            for (int ks = 0; ks < 2; ++ks) {
+                short8_t aa;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) aa[v] = (short)sAct[wv][r][16 * ks + 4 * g + v];
+                for (int v = 0; v < 8; ++v) aa[v] = (short)sAct[wv][r][32 * ks + 8 * g + v];
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
-                    short4_t bw;
+                    short8_t bw;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) bw[v] = (short)Wl[layer][(16 * nt + r) * NH + 16 * ks + 4 * g + v];
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aa, bw, acc[nt], 0, 0, 0);
+                    for (int v = 0; v < 8; ++v) bw[v] = (short)Wl[layer][(16 * nt + r) * NH + 32 * ks + 8 * g + v];
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, aa),
+                                                                      __builtin_bit_cast(bf16x8_t, bw), acc[nt], 0, 0,
+                                                                      0);
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -811,7 +816,7 @@ extern "C" int shg_screen_features(shg_ctx *c, const shg_shells *sh, shg_op op, 
     if ((rc = prep_shells(c, sh, LMAX, c->w, c->w_cap))) return rc;
     if ((rc = grow(c, c->stats, c->stats_cap, (size_t)sh->nshell * STAT + 1))) return rc;
     hipLaunchKernelGGL(k_shell_stats, dim3((sh->nshell + 255) / 256), dim3(256), 0, s, sh->nshell, sh->nprim,
-                       sh->prim_off, sh->exps, c->w, c->stats);
+                       sh->prim_off, sh->exps, c->w, op == SHG_OVERLAP || op == SHG_GAUSS ? 1 : 0, c->stats);
     if ((rc = screen_prepare(c))) return rc;
     hipLaunchKernelGGL(k_bound_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pairs, sh->center,
                        sh->l, c->stats, (int)op, omega, deriv ? 1 : 0, (const BoundTab *)c->bound_tab, feat, logb);
@@ -884,6 +889,11 @@ int plan_screen_enqueue(shg_ctx *c, hipStream_t s, const shg_shells *sh, const d
                         double tau, shg_mlp *mlp, float *work, uint8_t *keep, int32_t *bsum)
 {
     if (nops < 1 || nops > 5) return set_err(c, SHG_EINVAL, "screen: 1 to 5 operators");
+    // the statistics hold the moments of one operator family
+    const int gl = ops[0] == OP_OVERLAP || ops[0] == OP_GAUSS;
+    for (int o = 1; o < nops; ++o)
+        if ((ops[o] == OP_OVERLAP || ops[o] == OP_GAUSS) != (gl != 0))
+            return set_err(c, SHG_EINVAL, "screen: operators of one family only (overlap/Gaussian or Coulomb-like)");
     if (mlp && (nops != 1 || !mlp_covers(mlp, ops[0], deriv))) mlp = nullptr;
     if (mlp && mlp->ctx != c) return set_err(c, SHG_EINVAL, "screen: model belongs to another context");
     if (!c->bound_tab) return set_err(c, SHG_EINVAL, "screen: bound table not uploaded (screen_prepare)");
@@ -896,7 +906,7 @@ int plan_screen_enqueue(shg_ctx *c, hipStream_t s, const shg_shells *sh, const d
     }
     if (sh->nshell > 0)
         hipLaunchKernelGGL(k_shell_stats, dim3((sh->nshell + 255) / 256), dim3(256), 0, s, sh->nshell, sh->nprim,
-                           sh->prim_off, sh->exps, w, stats);
+                           sh->prim_off, sh->exps, w, gl, stats);
     if (n > 0 && keep) {
         float *feat = mlp ? work : nullptr, *logb = mlp ? work + (size_t)n * NF : nullptr;
         const unsigned g = (unsigned)((n + 255) / 256);

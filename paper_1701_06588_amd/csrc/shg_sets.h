@@ -21,7 +21,7 @@ namespace shg {
 
 constexpr int SET_KMAX = 8;     // exponents per set (K_a K_b <= 64: a lane per primitive pair)
 constexpr int SET_FMAX = 16;    // contracted functions per set
-constexpr int SET_KS = 10;      // radial scratch slots per function pair: k = 0..9
+constexpr int SET_KS = 10;      // radial orders of a set pair: k = 0..9
 constexpr int SET_STAGE = 80;   // staged doubles per item and pass: na nb rows NB NC <= 80
 
 // an l-block item: functions fa_rel0 .. fa_rel0+na-1 of set sa (l = la) against
@@ -30,9 +30,10 @@ struct __align__(16) SetItem {
     int32_t sa, sb;
     int32_t fa_rel0, fb_rel0;   // first function of the item, relative to its set
     int32_t row0, col0;         // block row / column of its first component
-    int32_t ld, nfb;            // row stride of the set-pair block (nsgf of B), functions of B
+    int32_t ld, orow;           // row stride of the set-pair block (nsgf of B); of the item's radial terms
     int64_t off;                // element offset of the set-pair block in out (dout: 3 off)
-    int64_t obase;              // radial scratch of the set pair: [fa_rel][fb_rel][SET_KS]
+    int64_t obase;              // radial terms of the item's first function pair: function pair (i, j)
+                                // of the item at obase + i orow + j NK, NK orders each
     int64_t blk;                // elements of the set-pair block (derivative block stride)
     int64_t pad;
 };
@@ -58,6 +59,9 @@ constexpr int set_fp_max(int la, int lb, bool D)
     int f = SET_STAGE / (set_rows(la, lb, D) * (2 * lb + 1) * (D ? 4 : 1));
     return f > 9 ? 9 : f;
 }
+
+// radial orders a function pair (la, lb) needs: k = max(la, lb) .. la + lb + deriv
+__host__ __device__ constexpr int set_nk(int la, int lb, int deriv) { return (la < lb ? la : lb) + 1 + deriv; }
 
 constexpr int SETBLK_TP = 64;
 
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_setblk(SetBlkArgs a, int64_t s
         const int f = r / NK, k = r - f * NK;
         const int fa = f / nb, fb = f - fa * nb;
         const SetItem &it = sIt[i];
-        sO[i * SO + r] = a.O[it.obase + ((int64_t)(it.fa_rel0 + fa) * it.nfb + it.fb_rel0 + fb) * SET_KS + PK::KLO + k];
+        sO[i * SO + r] = a.O[it.obase + (int64_t)fa * it.orow + fb * NK + k];
     }
     __syncthreads();
 

@@ -84,42 +84,60 @@ __global__ void k_prep_set_funcs(shg_sets s, double *w, int32_t *err)
     }
 }
 
+// radial terms of one function with angular momentum l against every function of B
+__device__ __forceinline__ int set_row_scratch(const shg_sets &s, int64_t fb0, int nfb, int l, int deriv)
+{
+    int t = 0;
+    for (int j = 0; j < nfb; ++j) t += set_nk(l, s.fun_l[fb0 + j], deriv);
+    return t;
+}
+
 // walks the l-block items of set pair (sa, sb) in a fixed order: A's functions
 // grouped by l, then B's, each group cut into chunks of at most the bin's
-// function counts; f(bin, item fields) per item
+// function counts; f(bin, fa, fb, row0, col0, o0, orow) per item, with o0 the
+// offset of its first function pair in the set pair's radial terms and orow
+// their row stride. The radial terms of a set pair are stored function pair
+// by function pair, row-major over (fa, fb), set_nk orders each.
 template <class F>
 __device__ __forceinline__ void for_items(const shg_sets &s, int sa, int sb, int deriv, F &&f)
 {
     const int64_t fa0 = s.fun_off[sa], fb0 = s.fun_off[sb];
     const int nfa = s.nfun[sa], nfb = s.nfun[sb];
     int row = 0;
+    int64_t orow0 = 0;
     for (int ia = 0; ia < nfa;) {
         const int la = s.fun_l[fa0 + ia];
         int ja = ia;
         while (ja < nfa && s.fun_l[fa0 + ja] == la) ++ja;
         const int na_tot = ja - ia;
+        const int srow = set_row_scratch(s, fb0, nfb, la, deriv);
         int col = 0;
+        int64_t ocol = 0;
         for (int ib = 0; ib < nfb;) {
             const int lb = s.fun_l[fb0 + ib];
             int jb = ib;
             while (jb < nfb && s.fun_l[fb0 + jb] == lb) ++jb;
             const int nb_tot = jb - ib;
+            const int nk = set_nk(la, lb, deriv);
             const int fpm = set_fp_max(la, lb, deriv != 0);
             const int nbc = min(nb_tot, fpm), nac = min(na_tot, max(1, fpm / nbc));
             for (int a0 = 0; a0 < na_tot; a0 += nac)
                 for (int b0 = 0; b0 < nb_tot; b0 += nbc) {
                     const int na = min(nac, na_tot - a0), nb = min(nbc, nb_tot - b0);
-                    f(set_bin(la, lb, na, nb), ia + a0, ib + b0, row + a0 * (2 * la + 1), col + b0 * (2 * lb + 1));
+                    f(set_bin(la, lb, na, nb), ia + a0, ib + b0, row + a0 * (2 * la + 1), col + b0 * (2 * lb + 1),
+                      orow0 + (int64_t)a0 * srow + ocol + (int64_t)b0 * nk, srow);
                 }
             col += nb_tot * (2 * lb + 1);
+            ocol += (int64_t)nb_tot * nk;
             ib = jb;
         }
         row += na_tot * (2 * la + 1);
+        orow0 += (int64_t)na_tot * srow;
         ia = ja;
     }
 }
 
-// per set pair: validation, radial-scratch size (nfa nfb SET_KS doubles) and
+// per set pair: validation, radial-scratch size (set_nk doubles per function pair) and
 // item counts per bin (LDS histogram, one global atomic per non-empty bin)
 __global__ __launch_bounds__(SET_TPB) void k_set_count(int64_t n, const int32_t *sp, shg_sets s, int deriv,
                                                        int64_t *osz, int32_t *hist, int32_t *err)
@@ -134,8 +152,11 @@ __global__ __launch_bounds__(SET_TPB) void k_set_count(int64_t n, const int32_t 
             atomicOr(err, ERR_PAIR_INDEX);
             osz[p] = 0;
         } else {
-            osz[p] = (int64_t)s.nfun[sa] * s.nfun[sb] * SET_KS;
-            for_items(s, sa, sb, deriv, [&](int bin, int, int, int, int) { atomicAdd(&lh[bin], 1); });
+            int64_t t = 0;
+            for_items(s, sa, sb, deriv, [&](int bin, int, int, int, int, int64_t, int) { atomicAdd(&lh[bin], 1); });
+            for (int fa = 0; fa < s.nfun[sa]; ++fa)
+                t += set_row_scratch(s, s.fun_off[sb], s.nfun[sb], s.fun_l[s.fun_off[sa] + fa], deriv);
+            osz[p] = t;
         }
     }
     __syncthreads();
@@ -161,7 +182,7 @@ __global__ __launch_bounds__(SET_TPB) void k_set_scatter(int64_t n, const int32_
         sb = sp[2 * p + 1];
         ok = sa >= 0 && sa < s.nset && sb >= 0 && sb < s.nset;
     }
-    if (ok) for_items(s, sa, sb, deriv, [&](int bin, int, int, int, int) { atomicAdd(&cnt[bin], 1); });
+    if (ok) for_items(s, sa, sb, deriv, [&](int bin, int, int, int, int, int64_t, int) { atomicAdd(&cnt[bin], 1); });
     __syncthreads();
     for (int b = threadIdx.x; b < SET_NBIN; b += SET_TPB) {
         if (cnt[b]) gb[b] = atomicAdd(&cursor[b], cnt[b]);
@@ -171,9 +192,9 @@ __global__ __launch_bounds__(SET_TPB) void k_set_scatter(int64_t n, const int32_
     if (ok) {
         const int ld = (int)nsgf[sb];
         const int64_t blk = nsgf[sa] * nsgf[sb];
-        for_items(s, sa, sb, deriv, [&](int bin, int fa, int fb, int row0, int col0) {
+        for_items(s, sa, sb, deriv, [&](int bin, int fa, int fb, int row0, int col0, int64_t o0, int orow) {
             const int32_t pos = gb[bin] + atomicAdd(&cnt[bin], 1);
-            items[pos] = SetItem{sa, sb, fa, fb, row0, col0, ld, s.nfun[sb], out_off[p], obase[p], blk, 0};
+            items[pos] = SetItem{sa, sb, fa, fb, row0, col0, ld, orow, out_off[p], obase[p] + o0, blk, 0};
         });
     }
 }
@@ -287,6 +308,7 @@ __global__ __launch_bounds__(64) void k_set_radial(int64_t n, const int32_t *sp,
     __shared__ double sG[SET_KS][64];
     __shared__ double sT[SET_KMAX * SET_FMAX];
     __shared__ double sWa[SET_FMAX * SET_KMAX], sWb[SET_FMAX * SET_KMAX];
+    __shared__ int sRow[SET_FMAX], sCol[LMAX + 1][SET_FMAX];   // radial-term offsets: row of fa, column of (l_a, fb)
     const int lane = threadIdx.x;
     const int64_t p = blockIdx.x;
     if (p >= n) return;   // uniform over the workgroup
@@ -324,6 +346,20 @@ __global__ __launch_bounds__(64) void k_set_radial(int64_t n, const int32_t *sp,
         const int f = e / kb, q = e - f * kb;
         sWb[e] = w[s.coef_off[fb0 + f] + q];
     }
+    if (lane <= LMAX) {
+        int t = 0;
+        for (int fb = 0; fb < nfb; ++fb) {
+            sCol[lane][fb] = t;
+            t += set_nk(lane, s.fun_l[fb0 + fb], deriv);
+        }
+        if (lane == 0) {   // rows: the running sum of each function's full row (its column total)
+            int r = 0;
+            for (int fa = 0; fa < nfa; ++fa) {
+                sRow[fa] = r;
+                r += set_row_scratch(s, fb0, nfb, s.fun_l[fa0 + fa], deriv);
+            }
+        }
+    }
     __syncthreads();
     double *dst = O + obase[p];
     for (int k = 0; k <= kmax; ++k) {
@@ -337,10 +373,11 @@ __global__ __launch_bounds__(64) void k_set_radial(int64_t n, const int32_t *sp,
         for (int e = lane; e < nfa * nfb; e += 64) {
             const int fa = e / nfb, fb = e - fa * nfb;
             const int la = s.fun_l[fa0 + fa], lb = s.fun_l[fb0 + fb];
-            if (k >= (la > lb ? la : lb) && k <= la + lb + (deriv ? 1 : 0)) {
+            const int klo = la > lb ? la : lb;
+            if (k >= klo && k <= la + lb + (deriv ? 1 : 0)) {
                 double o = 0.0;
                 for (int ia = 0; ia < ka; ++ia) o = fma(sWa[fa * ka + ia], sT[ia * nfb + fb], o);
-                dst[(int64_t)e * SET_KS + k] = o;
+                dst[sRow[fa] + sCol[la][fb] + (k - klo)] = o;
             }
         }
         __syncthreads();
