@@ -67,11 +67,11 @@ struct TileArgs {
     // pair whose analytic bound (shg_bound.h, per-shell statistics sstat) is
     // below stau -- or, with skeep set, whose decision flag skeep[pos] is 0 --
     // gets zero radial terms, so its block and d/dR_a blocks are written as
-    // zeros; its sorted position is appended to sskip (count in *sskip_n)
+    // zeros; without skeep the decision is stored as sflag[pos] (1 kept, 0 skipped)
     const double *sstat;
     const BoundTab *sbt;
     const uint8_t *skeep;
-    int32_t *sskip, *sskip_n;
+    uint8_t *sflag;
     double stau;
 };
 
@@ -205,12 +205,11 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
         const int G = TILE_THREADS / TP;
         const int i = tid / G, g = tid - (tid / G) * G;
         const bool live = i < tcount;
-        bool skip = false;
-        if (a.sstat) {
-            // screening: one thread per pair decides (bound, or the model's flag)
-            // before any radial work; the flags pass through the staging area,
-            // which is free until phase 2
-            int *sSkip = (int *)sT;
+        // screening (a.sstat set): one thread per pair decides, from the bound or the
+        // model's flag, before any radial work; the flags pass through the first
+        // 256 bytes of the staging area, which is free until phase 2
+        int *sSkip = (int *)sT;
+        const auto screen = [&]() {
             for (int q = tid; q < tcount; q += TILE_THREADS) {
                 bool sk;
                 if (a.skeep) {
@@ -225,12 +224,15 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
                                           fma(Y0, Y0, fma(Y1, Y1, Y2 * Y2)), a.op, a.omega, D ? 1 : 0, a.sbt, &vb,
                                           &Rr, &rm) < a.stau;
                 }
-                if (sk) a.sskip[atomicAdd(a.sskip_n, 1)] = (int32_t)(tstart + q);
+                if (a.sflag) a.sflag[tstart + q] = sk ? 0 : 1;
                 sSkip[q] = sk ? 1 : 0;
             }
-            __syncthreads();
-            skip = live && sSkip[i] != 0;
-        }
+        };
+        // screening inputs of this thread's pair (64-pair tiles: thread q decides pair
+        // q), loaded together with the pairs' own data
+        const bool bthread = TP == 64 && a.sstat && !a.skeep && tid < tcount;
+        PairRec rq{};
+        if (bthread) rq = a.rec[tstart + tid];
         const PairRec rc = a.rec[tstart + (live ? i : 0)];
         const int sa = rc.a, sb = rc.b;
         const double X0 = a.center[3 * sa] - a.center[3 * sb];
@@ -239,27 +241,66 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
         const double R2 = fma(X0, X0, fma(X1, X1, X2 * X2));   // fixed rounding order
         const int64_t oa = a.prim_off[sa], ob = a.prim_off[sb];
         const int ka = a.nprim[sa], kb = a.nprim[sb];
-        // a skipped pair gets no primitive work: its O^(k) stay zero, and so does its block
-        const bool work = live && !skip;
-        const int P = work ? ka * kb : 0;
         double O[PK::NK];
 #pragma unroll
         for (int k = 0; k < PK::NK; ++k) O[k] = 0.0;
         if (TP == 64) {
             // the pair's lanes stage its exponents and weights with independent
-            // loads, so the loop below waits on memory only for the Boys table
-            double *sP = (double *)((char *)sT + STG_OFF) + i * STG_STRIDE;
-            if (work) {
-                for (int q = g; q < ka; q += G) {
-                    sP[q] = a.exps[oa + q];
-                    sP[2 * KMAX + q] = a.w[oa + q];
+            // loads, so the loop below waits on memory only for the Boys table;
+            // the screening decisions are taken while those loads are in flight
+            static_assert(TILE_THREADS / 64 == 4 && (KMAX + 3) / 4 == 2, "two staged values per lane and shell");
+            // the bound reads statistics entries 0 .. 4 + la + lb + 1 of both shells
+            constexpr int NST = 4 + LA + LB + 2;
+            static_assert(NST <= STAT, "bound statistics of one shell");
+            double qa[NST], qb[NST], QX = 0, QY = 0, QZ = 0;
+            if (bthread) {
+#pragma unroll
+                for (int e = 0; e < NST; ++e) {
+                    qa[e] = a.sstat[(size_t)rq.a * STAT + e];
+                    qb[e] = a.sstat[(size_t)rq.b * STAT + e];
                 }
-                for (int q = g; q < kb; q += G) {
-                    sP[KMAX + q] = a.exps[ob + q];
-                    sP[3 * KMAX + q] = a.w[ob + q];
+                QX = a.center[3 * rq.a] - a.center[3 * rq.b];
+                QY = a.center[3 * rq.a + 1] - a.center[3 * rq.b + 1];
+                QZ = a.center[3 * rq.a + 2] - a.center[3 * rq.b + 2];
+            }
+            double *sP = (double *)((char *)sT + STG_OFF) + i * STG_STRIDE;
+            double va[2][2], vb[2][2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int q = g + 4 * u;
+                if (live && q < ka) {
+                    va[u][0] = a.exps[oa + q];
+                    va[u][1] = a.w[oa + q];
+                }
+                if (live && q < kb) {
+                    vb[u][0] = a.exps[ob + q];
+                    vb[u][1] = a.w[ob + q];
+                }
+            }
+            if (bthread) {
+                double vbd, Rr, rm;
+                const bool sk = shell_pair_bound(LA, LB, qa, qb, fma(QX, QX, fma(QY, QY, QZ * QZ)), a.op, a.omega,
+                                                 D ? 1 : 0, a.sbt, &vbd, &Rr, &rm) < a.stau;
+                a.sflag[tstart + tid] = sk ? 0 : 1;
+                sSkip[tid] = sk ? 1 : 0;
+            } else if (a.sstat && a.skeep && tid < tcount) {
+                sSkip[tid] = a.skeep[tstart + tid] == 0 ? 1 : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int q = g + 4 * u;
+                if (live && q < ka) {
+                    sP[q] = va[u][0];
+                    sP[2 * KMAX + q] = va[u][1];
+                }
+                if (live && q < kb) {
+                    sP[KMAX + q] = vb[u][0];
+                    sP[3 * KMAX + q] = vb[u][1];
                 }
             }
             __syncthreads();
+            // a skipped pair gets no primitive work: its O^(k) stay zero, and so does its block
+            const int P = live && !(a.sstat && sSkip[i] != 0) ? ka * kb : 0;
             for (int q = g; q < P; q += G) {
                 const int ia = q / kb, ib = q - ia * kb;
                 double gk[PK::NK];
@@ -269,6 +310,13 @@ __device__ __forceinline__ void tile_pairs(const TileArgs &a, int64_t tstart, in
                 for (int k = 0; k < PK::NK; ++k) O[k] = fma(ww, gk[k], O[k]);
             }
         } else {
+            bool skip = false;
+            if (a.sstat) {
+                screen();
+                __syncthreads();
+                skip = live && sSkip[i] != 0;
+            }
+            const int P = live && !skip ? ka * kb : 0;
             for (int q = g; q < P; q += G) {
                 const int ia = q / kb, ib = q - ia * kb;
                 double gk[PK::NK];

@@ -43,8 +43,8 @@ struct shg_plan {
     QTile *queue = nullptr;
     int ntiles = 0;                   // screened: the most tiles a queue can hold
     int *counter = nullptr;           // [0] tile counter; screened plans: the meta block below
-    // screening on the device (screened plans); meta: [0] tile counter; in-kernel
-    // mode [4] skipped; compacting mode [1] tiles, [2] kept, [3] skipped,
+    // screening on the device (screened plans); meta: [0] tile counter; compacting
+    // mode [1] tiles, [2] kept, [3] skipped,
     // [META_KS + c] kept start of class c, [META_TS + k] first tile of the k-th
     // class of the queue order
     int screened = 0;
@@ -52,9 +52,9 @@ struct shg_plan {
     double tau = 0;
     shg_mlp *mlp = nullptr;
     PairRec *rec_all = nullptr;       // class-sorted records of every pair
-    uint8_t *keep = nullptr;          // [n] decision per sorted position
+    uint8_t *keep = nullptr;          // [n] decision per sorted position (1 kept)
     int32_t *bsum = nullptr;          // [2][nblk + 1]: kept per scan block, exclusive scan
-    int32_t *skip = nullptr;          // [n] sorted positions of the skipped pairs
+    int32_t *skip = nullptr;          // [n] sorted positions of the skipped pairs (compacting mode)
     double *stats = nullptr;          // per-shell screening statistics
     float *swork = nullptr;           // model inference scratch (n * 15 floats)
     int64_t cls_all[NCLASS + 1] = {}; // class starts of the unscreened sorted order
@@ -90,9 +90,8 @@ static TileArgs plan_tile_args(const shg_plan *p)
     if (p->screened && !p->compact) {
         ta.sstat = p->stats;
         ta.sbt = (const BoundTab *)p->ctx->bound_tab;
-        ta.skeep = p->mlp ? p->keep : nullptr;
-        ta.sskip = p->skip;
-        ta.sskip_n = p->counter + 4;
+        ta.skeep = p->mlp ? p->keep : nullptr;    // the model's flags, from the stage
+        ta.sflag = p->mlp ? nullptr : p->keep;    // else the kernel records the bound's decisions
         ta.stau = p->tau;
     }
     if (plan_mono(p->op)) {
@@ -293,7 +292,7 @@ static int plan_screen_stage(shg_plan *p, hipStream_t s)
     const int64_t n = p->n;
     if (n == 0) return 0;
     if (!p->compact) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 8);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
         int rc = plan_screen_enqueue(c, s, &p->sh, p->w, p->stats, p->rec_all, n, 1, &p->op, &p->omega, p->deriv,
                                      p->tau, p->mlp, p->swork, p->mlp ? p->keep : nullptr, nullptr);
         if (rc) return rc;
@@ -573,6 +572,14 @@ __global__ void k_make_recs(int64_t n, const int32_t *order, const int32_t *pair
 
 // reads the decision of the last execution back: kept and skipped counts and
 // the kept class starts (synchronises the context stream)
+static int plan_read_flags(const shg_plan *p, std::vector<uint8_t> &f)
+{
+    f.resize(p->n);
+    if (p->n > 0 && hipMemcpy(f.data(), p->keep, p->n, hipMemcpyDeviceToHost) != hipSuccess)
+        return set_err(p->ctx, SHG_EDEVICE, "plan: read-back failed");
+    return 0;
+}
+
 static int plan_read_meta(const shg_plan *p, int64_t *kept, int64_t *skipped, int64_t *ks)
 {
     shg_ctx *c = p->ctx;
@@ -586,19 +593,17 @@ static int plan_read_meta(const shg_plan *p, int64_t *kept, int64_t *skipped, in
             for (int cls = 0; cls <= NCLASS; ++cls) ks[cls] = m[META_KS + cls];
         return 0;
     }
-    // in-kernel mode: skip count in m[4], positions in p->skip
-    const int64_t ns = m[4];
+    // in-kernel mode: one decision flag per class-sorted position
+    std::vector<uint8_t> f;
+    if (int rc = plan_read_flags(p, f)) return rc;
+    std::vector<int64_t> cnt(NCLASS, 0);
+    int64_t ns = 0;
+    for (int cls = 0; cls < NCLASS; ++cls)
+        for (int64_t q = p->cls_all[cls]; q < p->cls_all[cls + 1]; ++q) cnt[cls] += f[q] == 0;
+    for (int cls = 0; cls < NCLASS; ++cls) ns += cnt[cls];
     if (kept) *kept = p->n - ns;
     if (skipped) *skipped = ns;
     if (ks) {
-        // kept per class = class size minus the skipped positions inside it
-        std::vector<int32_t> pos(ns);
-        if (ns > 0 && hipMemcpy(pos.data(), p->skip, ns * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-            return set_err(c, SHG_EDEVICE, "plan: read-back failed");
-        std::vector<int64_t> cnt(NCLASS, 0);
-        for (int32_t q : pos)
-            for (int cls = 0; cls < NCLASS; ++cls)
-                if (q >= p->cls_all[cls] && q < p->cls_all[cls + 1]) ++cnt[cls];
         ks[0] = 0;
         for (int cls = 0; cls < NCLASS; ++cls) ks[cls + 1] = ks[cls] + (p->cls_all[cls + 1] - p->cls_all[cls]) - cnt[cls];
     }
@@ -634,7 +639,7 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
     if (n > 0) {
         e = hipMalloc((void **)&p->rec_all, n * sizeof(PairRec));
         if (e == hipSuccess) e = hipMalloc((void **)&p->keep, ((n + 15) / 16 * 16) * sizeof(uint8_t));
-        if (e == hipSuccess) e = hipMalloc((void **)&p->skip, n * sizeof(int32_t));
+        if (e == hipSuccess && p->compact) e = hipMalloc((void **)&p->skip, n * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc((void **)&p->bsum, 2 * (nb + 1) * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc((void **)&p->stats, plan_screen_stats_doubles(sh->nshell) * sizeof(double));
         if (e == hipSuccess && mlp) e = hipMalloc((void **)&p->swork, (size_t)n * 15 * sizeof(float));
@@ -811,9 +816,18 @@ extern "C" int64_t shg_plan_skipped(const shg_plan *p, int32_t *ids, int64_t cap
     if (rc) return rc;
     if (ids && cap > 0 && ns > 0) {
         const int64_t m = std::min(ns, cap);
-        std::vector<int32_t> pos(m), order(p->n);
-        if (hipMemcpy(pos.data(), p->skip, m * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(order.data(), p->order, p->n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        std::vector<int32_t> pos, order(p->n);
+        if (p->compact) {
+            pos.resize(m);
+            if (hipMemcpy(pos.data(), p->skip, m * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+                return set_err(p->ctx, SHG_EDEVICE, "shg_plan_skipped: read-back failed");
+        } else {
+            std::vector<uint8_t> f;
+            if ((rc = plan_read_flags(p, f))) return rc;
+            for (int64_t q = 0; q < p->n && (int64_t)pos.size() < m; ++q)
+                if (f[q] == 0) pos.push_back((int32_t)q);
+        }
+        if (hipMemcpy(order.data(), p->order, p->n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
             return set_err(p->ctx, SHG_EDEVICE, "shg_plan_skipped: read-back failed");
         for (int64_t i = 0; i < m; ++i) ids[i] = order[pos[i]];
     }
@@ -858,10 +872,7 @@ extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
     const TileArgs ta = plan_tile_args(p);
     double tot = 0;
     for (int r = 0; r < reps; ++r) {
-        // in-kernel screening appends to the skip list: its count restarts too
-        if (p->mode >= 1)
-            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0,
-                               p->screened && !p->compact ? 8 : 1);
+        if (p->mode >= 1) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, 1);
         HIP_TRY(c, hipEventRecord(e0, c->stream));
         plan_radial(p, c->stream);
         if (p->mode == 1) {
