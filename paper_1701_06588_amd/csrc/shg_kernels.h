@@ -150,7 +150,9 @@ constexpr int tile_smem_bytes(int tp, int rows_pp)
 // per CU from l_a = 7 with derivatives, three otherwise).
 constexpr int sched_rows(int la, int lb, bool D)
 {
-    constexpr int rows_d[5][5] = {{1, 1, 1, 1, 1}, {3, 3, 3, 3, 3}, {5, 5, 5, 5, 4}, {7, 7, 7, 5, 4}, {9, 9, 7, 5, 4}};
+    // (2,2) stages four rows so that the light classes (la + lb <= 4) fit 53 KiB:
+    // three workgroups per CU for their persistent kernel
+    constexpr int rows_d[5][5] = {{1, 1, 1, 1, 1}, {3, 3, 3, 3, 3}, {5, 5, 4, 5, 4}, {7, 7, 7, 5, 4}, {9, 9, 7, 5, 4}};
     if (la <= 4) return D ? rows_d[la][lb] : 2 * la + 1;
     const int budget = (D && la >= 7) ? 80 * 1024 - 256 : 53 * 1024;
     int rows = 2 * la + 1;

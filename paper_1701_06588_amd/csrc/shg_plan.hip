@@ -42,6 +42,11 @@ struct shg_plan {
     double *w = nullptr;              // folded weights (plan-owned)
     QTile *queue = nullptr;
     int ntiles = 0;                   // screened: the most tiles a queue can hold
+    // persistent mode: heavy classes (the first nt_h tiles of the queue) and light
+    // classes each run by a kernel of their own group (split), or one kernel of
+    // all classes (compacting screened plans)
+    int split = 0, nt_h = 0, grid_h = 0, grid_l = 0;
+    size_t smem_h = 0, smem_l = 0;
     int *counter = nullptr;           // [0] tile counter; screened plans: the meta block below
     // screening on the device (screened plans); meta: [0] tile counter; compacting
     // mode [1] tiles, [2] kept, [3] skipped,
@@ -292,7 +297,7 @@ static int plan_screen_stage(shg_plan *p, hipStream_t s)
     const int64_t n = p->n;
     if (n == 0) return 0;
     if (!p->compact) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, p->split ? 2 : 1);
         int rc = plan_screen_enqueue(c, s, &p->sh, p->w, p->stats, p->rec_all, n, 1, &p->op, &p->omega, p->deriv,
                                      p->tau, p->mlp, p->swork, p->mlp ? p->keep : nullptr, nullptr);
         if (rc) return rc;
@@ -317,14 +322,31 @@ static int plan_screen_stage(shg_plan *p, hipStream_t s)
     return 0;
 }
 
+static void persist_entry(int deriv, int group, persist_fn *f, persist_occ_fn *occ)
+{
+    if (deriv) persist_entry_d1(group, f, occ);
+    else persist_entry_d0(group, f, occ);
+}
+
 static void plan_launch_persist(const shg_plan *p, hipStream_t s, const TileArgs &ta)
 {
     persist_fn f;
     persist_occ_fn occ;
-    if (p->deriv) persist_entry_d1(&f, &occ);
-    else persist_entry_d0(&f, &occ);
-    // a compacting screened plan's kernel reads the number of tiles from counter[1]
-    f(s, p->grid, p->smem, ta, p->queue, p->screened && p->compact ? -1 : p->ntiles, p->counter);
+    if (!p->split) {
+        persist_entry(p->deriv, PG_ALL, &f, &occ);
+        // a compacting screened plan's kernel reads the number of tiles from counter[1]
+        f(s, p->grid, p->smem, ta, p->queue, p->screened && p->compact ? -1 : p->ntiles, p->counter);
+        return;
+    }
+    // heavy tiles first, on tile counter [0]; the light ones after, on counter [1]
+    if (p->nt_h > 0) {
+        persist_entry(p->deriv, PG_HEAVY, &f, &occ);
+        f(s, p->grid_h, p->smem_h, ta, p->queue, p->nt_h, p->counter);
+    }
+    if (p->ntiles > p->nt_h) {
+        persist_entry(p->deriv, PG_LIGHT, &f, &occ);
+        f(s, p->grid_l, p->smem_l, ta, p->queue + p->nt_h, p->ntiles - p->nt_h, p->counter + 1);
+    }
 }
 
 // shell preparation and the stage before the evaluation kernels (radial terms
@@ -341,7 +363,7 @@ static int plan_enqueue_stage(shg_plan *p, hipStream_t s)
         int rc = plan_screen_stage(p, s);   // also clears the tile counter
         if (rc) return rc;
     } else if (p->mode == 1 && p->ntiles > 0) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, 1);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->counter, 0, p->split ? 2 : 1);
     }
     HIP_TRY(c, hipGetLastError());
     return 0;
@@ -407,81 +429,101 @@ static int plan_capture(shg_plan *p)
     return rc;
 }
 
-// builds the tile queue of the persistent kernels: tiles
-// of 64 pairs and the compiled schedule of each class (its LDS need is the
-// dynamic LDS of the launch)
+// builds the tile queue of the persistent kernels: tiles of 64 pairs and the
+// compiled schedule of each class (its LDS need sets the dynamic LDS of the
+// launch). Split plans queue the heavy classes' tiles first, then the light
+// ones; the tile order applies within each part.
 static int plan_build_queue(shg_plan *p)
 {
     shg_ctx *c = p->ctx;
+    const bool split = !(p->screened && p->compact);
     std::vector<QTile> q;
-    std::vector<std::pair<double, int>> cls_cost;
-    for (int cls = 0; cls < NCLASS; ++cls) {
-        int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
-        double per_pair = (double)(2 * la + 1) * (2 * lb + 1) * (p->deriv ? 4 : 1) + 4.0 * (la + lb + 1);
-        cls_cost.push_back({-per_pair, cls});
-    }
-    std::sort(cls_cost.begin(), cls_cost.end());
-    size_t smem = 0;
+    size_t smem_g[3] = {0, 0, 0};
+    int nt_g[3] = {0, 0, 0};
     constexpr int TP = 64;
-    for (auto &cc : cls_cost) {
-        int cls = cc.second;
-        int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
-        int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
-        if (b1 > b0) {
-            size_t b = (size_t)tile_smem_bytes_rt(TP, sched_rows(la, lb, p->deriv != 0), lb, p->deriv != 0);
-            smem = std::max(smem, b);
+    const int groups[2] = {PG_HEAVY, PG_LIGHT};
+    for (int gi = 0; gi < (split ? 2 : 1); ++gi) {
+        const int group = split ? groups[gi] : PG_ALL;
+        std::vector<std::pair<double, int>> cls_cost;
+        for (int cls = 0; cls < NCLASS; ++cls) {
+            int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
+            if (!persist_has(group, la, lb)) continue;
+            double per_pair = (double)(2 * la + 1) * (2 * lb + 1) * (p->deriv ? 4 : 1) + 4.0 * (la + lb + 1);
+            cls_cost.push_back({-per_pair, cls});
         }
-        for (int64_t s0 = b0; s0 < b1; s0 += TP) q.push_back(QTile{cls, (int32_t)std::min<int64_t>(TP, b1 - s0), s0});
-    }
-    if (p->qorder == 1) {
-        // alternate from the two ends of the heaviest-first order: co-resident
-        // workgroups then mix arithmetic-heavy tiles with light, load/store-bound
-        // ones, and the launch ends on tiles of middle weight
-        std::vector<QTile> z;
-        z.reserve(q.size());
-        size_t lo = 0, hi = q.size();
-        while (lo < hi) {
-            z.push_back(q[lo++]);
-            if (lo < hi) z.push_back(q[--hi]);
+        std::sort(cls_cost.begin(), cls_cost.end());
+        std::vector<QTile> g;
+        for (auto &cc : cls_cost) {
+            int cls = cc.second;
+            int64_t b0 = p->cls_start[cls], b1 = p->cls_start[cls + 1];
+            int la = cls / (LMAX + 1), lb = cls % (LMAX + 1);
+            if (b1 > b0) {
+                size_t b = (size_t)tile_smem_bytes_rt(TP, sched_rows(la, lb, p->deriv != 0), lb, p->deriv != 0);
+                smem_g[group] = std::max(smem_g[group], b);
+            }
+            for (int64_t s0 = b0; s0 < b1; s0 += TP)
+                g.push_back(QTile{cls, (int32_t)std::min<int64_t>(TP, b1 - s0), s0});
         }
-        q.swap(z);
-    } else if (p->qorder == 2) {
-        // round robin over the classes, heaviest class first in every round
-        std::vector<std::vector<QTile>> per(NCLASS);
-        std::vector<int> cls_seq;
-        for (const auto &t : q) {
-            if (per[t.cls].empty()) cls_seq.push_back(t.cls);
-            per[t.cls].push_back(t);
+        if (p->qorder == 1) {
+            // alternate from the two ends of the heaviest-first order: co-resident
+            // workgroups then mix arithmetic-heavy tiles with light, load/store-bound
+            // ones, and the launch ends on tiles of middle weight
+            std::vector<QTile> z;
+            z.reserve(g.size());
+            size_t lo = 0, hi = g.size();
+            while (lo < hi) {
+                z.push_back(g[lo++]);
+                if (lo < hi) z.push_back(g[--hi]);
+            }
+            g.swap(z);
+        } else if (p->qorder == 2) {
+            // round robin over the classes, heaviest class first in every round
+            std::vector<std::vector<QTile>> per(NCLASS);
+            std::vector<int> cls_seq;
+            for (const auto &t : g) {
+                if (per[t.cls].empty()) cls_seq.push_back(t.cls);
+                per[t.cls].push_back(t);
+            }
+            std::vector<QTile> z;
+            z.reserve(g.size());
+            std::vector<size_t> pos(NCLASS, 0);
+            while (z.size() < g.size())
+                for (int cls : cls_seq)
+                    if (pos[cls] < per[cls].size()) z.push_back(per[cls][pos[cls]++]);
+            g.swap(z);
         }
-        std::vector<QTile> z;
-        z.reserve(q.size());
-        std::vector<size_t> pos(NCLASS, 0);
-        while (z.size() < q.size())
-            for (int cls : cls_seq)
-                if (pos[cls] < per[cls].size()) z.push_back(per[cls][pos[cls]++]);
-        q.swap(z);
+        nt_g[group] = (int)g.size();
+        q.insert(q.end(), g.begin(), g.end());
     }
     if (q.size() >= (size_t)1 << 31) return set_err(c, SHG_EINVAL, "plan: too many tiles");
     if (p->queue) { HIP_TRY(c, hipFree(p->queue)); p->queue = nullptr; }
     p->ntiles = (int)q.size();
-    p->smem = smem;
-    if (smem > (size_t)PERSIST_MAX_SMEM && p->mode == 1)
+    p->split = split ? 1 : 0;
+    p->nt_h = nt_g[PG_HEAVY];
+    p->smem_h = smem_g[PG_HEAVY];
+    p->smem_l = smem_g[PG_LIGHT];
+    p->smem = split ? std::max(p->smem_h, p->smem_l) : smem_g[PG_ALL];
+    if (p->smem > (size_t)PERSIST_MAX_SMEM && p->mode == 1)
         return set_err(c, SHG_EINVAL, "plan: tile shapes need %zu bytes of LDS, more than the persistent kernel allows",
-                       smem);
+                       p->smem);
     if (!q.empty()) {
         HIP_TRY(c, hipMalloc((void **)&p->queue, q.size() * sizeof(QTile)));
         HIP_TRY(c, hipMemcpy(p->queue, q.data(), q.size() * sizeof(QTile), hipMemcpyHostToDevice));
     }
-    persist_fn f;
-    persist_occ_fn occ;
-    if (p->deriv) persist_entry_d1(&f, &occ);
-    else persist_entry_d0(&f, &occ);
     hipDeviceProp_t prop;
     HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
-    // the per-class kernels raise their LDS limit on first launch; make sure that
-    // happened before a graph capture by launching nothing here but the query
-    int per_cu = occ(p->smem);
-    p->grid = std::max(1, std::min(p->ntiles, prop.multiProcessorCount * per_cu));
+    // the occupancy queries also raise the kernels' LDS limits, before any graph capture
+    const auto grid_of = [&](int group, size_t smem, int nt) {
+        persist_fn f;
+        persist_occ_fn occ;
+        persist_entry(p->deriv, group, &f, &occ);
+        return std::max(1, std::min(nt, prop.multiProcessorCount * occ(smem)));
+    };
+    if (split) {
+        p->grid_h = grid_of(PG_HEAVY, p->smem_h, p->nt_h);
+        p->grid_l = grid_of(PG_LIGHT, p->smem_l, p->ntiles - p->nt_h);
+    }
+    p->grid = grid_of(PG_ALL, p->smem, p->ntiles);
     return 0;
 }
 
@@ -630,6 +672,7 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
         return fail(set_err(c, SHG_EINVAL, "%s: the persistent kernel cannot take these tiles", what));
     p->screened = 1;
     p->compact = (flags & SHG_PLAN_COMPACT) ? 1 : 0;
+    if (p->compact) p->split = 0;   // its queue is built on the device for the all-class kernel
     p->mode = 1;
     p->tau = tau;
     p->mlp = mlp;
@@ -872,7 +915,8 @@ extern "C" int shg_plan_kernel_ms(shg_plan *p, int reps, double *ms)
     const TileArgs ta = plan_tile_args(p);
     double tot = 0;
     for (int r = 0; r < reps; ++r) {
-        if (p->mode >= 1) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, 1);
+        if (p->mode >= 1)
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, p->counter, 0, p->split ? 2 : 1);
         HIP_TRY(c, hipEventRecord(e0, c->stream));
         plan_radial(p, c->stream);
         if (p->mode == 1) {
