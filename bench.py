@@ -71,9 +71,10 @@ def kernel_source_hash() -> str:
 
 
 def stored_traffic():
-    """HBM bytes per launch of k_persist<true> on this workload from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain
-    copy), or None when there is none or the kernel sources changed since"""
+    """HBM bytes per evaluation (the heavy- and light-class launches of k_persist<true>)
+    on this workload from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated on a plain copy), or None when there is none or the
+    kernel sources changed since"""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -302,7 +303,9 @@ def main():
     tfl = f_launch / (ms_launch / 1e3) / 1e12
     roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(),
-                "kernel": "shg::k_persist<true>", "avg_launch_ms": round(ms_launch, 4),
+                "kernel": "shg::k_persist<true, heavy> + shg::k_persist<true, light> (one evaluation: the "
+                          "heavy-class and the light-class persistent launches of a plan)",
+                "avg_launch_ms": round(ms_launch, 4),
                 "alg_bytes_per_launch": int(b_launch), "alg_flops_per_launch": int(f_launch),
                 "fp64_tflops": round(tfl, 3), "fp64_frac": round(tfl / FP64_PEAK_TFLOPS, 4),
                 "per_op_ms": {k[0]: round(k[1], 4) for k in kern},
