@@ -183,7 +183,8 @@ def main():
                     help="pairs timed on the CPU oracle with all host threads (x 5 operators; 0 = skip)")
     ap.add_argument("--cpu-sample-1core", type=int, default=2000,
                     help="pairs timed on the CPU oracle with one thread (x 5 operators; 0 = skip)")
-    ap.add_argument("--tile-order", default="alternating", choices=["alternating", "heaviest-first", "auto"],
+    ap.add_argument("--tile-order", default="round-robin",
+                    choices=["round-robin", "alternating", "heaviest-first", "auto"],
                     help="tile order of the plans' persistent queue (auto: timed by the plan autotuner)")
     ap.add_argument("--no-extra", action="store_true", help="skip the measurements of the other workloads")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
@@ -616,7 +617,9 @@ def run_extras(args, eng, shg, inputs, workmodel, np, torch):
                                      ("bound, compacting stage", None, shg.PLAN_COMPACT)):
                 pl = shg.Plan(eng, dsh5, op, w5.omega[op], p5, oo5, got5, None, shg.PLAN_PERSISTENT | fl, tau=tau5,
                               mlp=model)
-                pl.set_tile_order(args.tile_order if args.tile_order != "auto" else "alternating")
+                # (a compacting plan builds its queue on the device, in the first two orders only)
+                order = args.tile_order if args.tile_order != "auto" else "round-robin"
+                pl.set_tile_order("alternating" if fl and order == "round-robin" else order)
                 ms_v, _ = timed(eng, pl.execute, 3, 1)
                 bad5, mass5 = compare_chunked(got5, ref5)
                 abl["variants"].setdefault(vname, {})[op] = {

@@ -219,16 +219,18 @@ int shg_set_aab_chunk(shg_ctx *ctx, int64_t chunk);
  * output buffers (all device pointers, kept by reference, owned by the caller
  * and required to outlive the plan). Creation runs shg_pairs / shg_pairs_deriv
  * once (dout NULL: values only), which validates the input and bins the pairs
- * by class, copies the class-sorted order, builds a tile work queue (heavy
- * and light classes alternating) and, unless SHG_PLAN_NO_GRAPH, records the evaluation
- * (shell preparation + class kernels) in a hipGraph. Execution replays it with
+ * by class, copies the class-sorted order, builds a tile work queue (round
+ * robin over the classes by default) and, unless SHG_PLAN_NO_GRAPH, records the
+ * evaluation (shell preparation + class kernels) in a hipGraph. Execution replays it with
  * no host synchronisation and no binning; new centers, exponents or raw
  * coefficients written into the same buffers are picked up, but the shells'
  * l and K and the pair list must not change (they are not re-validated).
- *   flags: SHG_PLAN_PERSISTENT  one persistent class-binned kernel over the
- *                               tile queue (64-pair tiles, each class with its
- *                               compiled tile schedule) instead of one launch
- *                               per class (with the tuned tile shapes)
+ *   flags: SHG_PLAN_PERSISTENT  persistent class-binned kernels over the tile
+ *                               queue (64-pair tiles, each class with its
+ *                               compiled tile schedule; one kernel for the
+ *                               heavy classes la + lb >= 5, then one for the
+ *                               light ones) instead of one launch per class
+ *                               (with the tuned tile shapes)
  *          SHG_PLAN_NO_GRAPH    enqueue the kernels on every execute */
 #define SHG_PLAN_PERSISTENT 1u
 #define SHG_PLAN_NO_GRAPH   2u

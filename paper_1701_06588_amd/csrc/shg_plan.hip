@@ -36,7 +36,7 @@ struct shg_plan {
     double *out = nullptr, *dout = nullptr;
     int deriv = 0;
     int mode = 0;                     // 0 per-class launches, 1 persistent
-    int qorder = 1;                   // tile order: 0 heaviest first, 1 alternating ends, 2 round robin
+    int qorder = 2;                   // tile order: 0 heaviest first, 1 alternating ends, 2 round robin
     int32_t *order = nullptr;         // class-sorted pair ids (plan-owned)
     PairRec *rec = nullptr;           // class-sorted pair records (plan-owned; compacting: the kept ones)
     double *w = nullptr;              // folded weights (plan-owned)
@@ -672,7 +672,10 @@ extern "C" int shg_plan_create_screened(shg_ctx *c, const shg_shells *sh, shg_op
         return fail(set_err(c, SHG_EINVAL, "%s: the persistent kernel cannot take these tiles", what));
     p->screened = 1;
     p->compact = (flags & SHG_PLAN_COMPACT) ? 1 : 0;
-    if (p->compact) p->split = 0;   // its queue is built on the device for the all-class kernel
+    if (p->compact) {
+        p->split = 0;     // its queue is built on the device for the all-class kernel,
+        p->qorder = 1;    // in the first two orders only
+    }
     p->mode = 1;
     p->tau = tau;
     p->mlp = mlp;
