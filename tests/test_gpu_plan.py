@@ -101,3 +101,47 @@ def test_plan_autotune_selects_a_mode(engine):
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
     plan.close()
+
+
+@pytest.mark.parametrize("group", ["light", "heavy"])
+@pytest.mark.parametrize("deriv", [False, True])
+def test_persistent_plan_single_class_group(engine, group, deriv):
+    """Persistent plans run the heavy classes (la + lb >= 5) and the light ones
+    as two kernels; a pair list with only one group leaves the other launch
+    empty. Every tile order gives the plain path's blocks bitwise, screened
+    plans too (skipped blocks zero)."""
+    import torch
+    from paper_1701_06588_amd import shg
+    w = inputs.small_pairs(81, 6000)
+    sh = w.shells
+    s = sh.l[w.pairs[:, 0]] + sh.l[w.pairs[:, 1]]
+    keep = s >= 5 if group == "heavy" else s <= 4
+    w = inputs.Workload(f"small6000-{group}", sh, np.ascontiguousarray(w.pairs[keep]), w.ops, w.omega, True,
+                        n_atoms=w.n_atoms)
+    print(f"case single group {group} deriv={deriv} n={len(w.pairs)}", flush=True)
+    dsh, pairs, oo, out, dout = _setup(engine, w, deriv)
+    engine.pairs(dsh, "erfc", w.omega["erfc"], pairs, oo, out, dout)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    dref = dout.clone() if deriv else None
+    for order in ("heaviest-first", "alternating", "round-robin"):
+        plan = shg.Plan(engine, dsh, "erfc", w.omega["erfc"], pairs, oo, out, dout, shg.PLAN_PERSISTENT)
+        plan.set_tile_order(order)
+        out.fill_(float("nan"))
+        if deriv:
+            dout.fill_(float("nan"))
+        plan.execute()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), order
+        if deriv:
+            assert torch.equal(dout, dref), order
+        plan.close()
+    plan = shg.Plan(engine, dsh, "erfc", w.omega["erfc"], pairs, oo, out, dout, shg.PLAN_PERSISTENT, tau=1e-12)
+    out.fill_(float("nan"))
+    plan.execute()
+    torch.cuda.synchronize()
+    got, r = out.cpu().numpy(), ref.cpu().numpy()
+    assert np.all((got == r) | (got == 0))
+    kept, _ = plan.stats()
+    assert kept + len(plan.skipped()) == len(w.pairs)
+    plan.close()
