@@ -168,9 +168,9 @@ struct GauntArgs {
 // A workgroup takes GQ triples and one component (value or one of x, y, z):
 // it stages their Y blocks (every L_a of the class, coalesced reads) and the
 // class's Gaunt lists (at most 2 terms per L_a value) in LDS, then computes
-// out[ma][mt][mb] = sum over the list of (ma, mt) of G * Y_L[M][mb] with
-// consecutive threads on consecutive output elements (coalesced stores). The
-// class is a template parameter so that all index arithmetic is by constants.
+// out[ma][mt][mb] = sum over the list of (ma, mt) of G * Y_L[M][mb], a thread
+// per (triple, ma, mt) row of NB values. The class is a template parameter so
+// that all index arithmetic is by constants.
 constexpr int GQ = 8;
 
 template <int LA, int LT, int LB, int NC>
@@ -212,21 +212,28 @@ __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
         sY[t] = c == 0 ? a.Yv[yb + r] : a.Yd[3 * yb + 3 * loffc(nL) + (c - 1) * (2 * L + 1) * NB + (r - loffc(nL))];
     }
     __syncthreads();
-    for (int e = tid; e < nq * SZ; e += 256) {
-        const int ql = e / SZ, rem = e - ql * SZ;
-        const int mb = rem % NB, amt = rem / NB;
+    // a thread takes one (triple, ma, mt) row: all NB values of mb at once, so
+    // each Gaunt term's coefficient and (L, M) are read once for NB products;
+    // consecutive threads write consecutive rows (contiguous stores)
+    for (int e = tid; e < nq * NAT; e += 256) {
+        const int ql = e / NAT, amt = e - ql * NAT;
         const int2 se = s_idx[amt];
         const double *y = sY + ql * YS;
-        double v = 0.0;
+        double v[NB];
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb) v[mb] = 0.0;
         for (int k = se.x; k < se.x + se.y && k < gn; ++k) {
             const int L = s_lm[k].x, M = s_lm[k].y;
-            v = fma(s_g[k], y[loffc((L - LAMIN) / 2) + (M + L) * NB + mb], v);
+            const double g = s_g[k];
+            const int n = (L - LAMIN) / 2;
+            const double *yl = y + NB * (n * (2 * LAMIN + 1) + 2 * n * (n - 1)) + (M + L) * NB;
+#pragma unroll
+            for (int mb = 0; mb < NB; ++mb) v[mb] = fma(g, yl[mb], v[mb]);
         }
         const int64_t off = s_off[ql];
-        if (c == 0)
-            a.out[off + rem] = v;
-        else
-            a.dout[3 * off + (int64_t)(c - 1) * SZ + rem] = v;
+        double *dst = c == 0 ? a.out + off + amt * NB : a.dout + 3 * off + (int64_t)(c - 1) * SZ + amt * NB;
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb) dst[mb] = v[mb];
     }
 }
 
