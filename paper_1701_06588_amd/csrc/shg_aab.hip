@@ -165,13 +165,15 @@ struct GauntArgs {
     int la, lt, lb, nc, lamin;
 };
 
-// A workgroup takes GQ triples and one component (value or one of x, y, z):
-// it stages their Y blocks (every L_a of the class, coalesced reads) and the
-// class's Gaunt lists (at most 2 terms per L_a value) in LDS, then computes
-// out[ma][mt][mb] = sum over the list of (ma, mt) of G * Y_L[M][mb], a thread
-// per (triple, ma, mt) row of NB values. The class is a template parameter so
-// that all index arithmetic is by constants.
+// A group is GQ triples and one component (value or one of x, y, z). Each
+// workgroup stages the class's Gaunt lists (at most 2 terms per L_a value) in
+// LDS once and then takes groups blockIdx.x, blockIdx.x + gridDim.x, ...: it
+// stages the group's Y blocks (every L_a of the class, coalesced reads) and
+// computes out[ma][mt][mb] = sum over the list of (ma, mt) of G * Y_L[M][mb], a
+// thread per (triple, ma, mt) row of NB values. The class is a template
+// parameter so that all index arithmetic is by constants.
 constexpr int GQ = 8;
+constexpr int GAUNT_GRID = 2048;   // workgroups per launch at most (eight per CU)
 
 template <int LA, int LT, int LB, int NC>
 __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
@@ -180,16 +182,13 @@ __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
     constexpr int LAMIN = LA > LT ? LA - LT : LT - LA, NLA = (LA + LT - LAMIN) / 2 + 1, GMAX = NAT * 2 * NLA;
     // offset of the L_a block with index n (L_a = LAMIN + 2n) in a triple's Y: sum of (2L'+1) NB, L' < L_a
     constexpr auto loffc = [](int n) constexpr { return NB * (n * (2 * LAMIN + 1) + 2 * n * (n - 1)); };
-    constexpr int YS = loffc(NLA);
+    constexpr int YS = loffc(NLA), NIT = (GQ * YS + 255) / 256;
     __shared__ int2 s_idx[NAT];
     __shared__ int2 s_lm[GMAX];
     __shared__ double s_g[GMAX];
     __shared__ double sY[GQ * YS];
     __shared__ int64_t s_off[GQ];
     const int tid = threadIdx.x;
-    const int c = (int)(blockIdx.x % NC);
-    const int64_t q0 = (int64_t)(blockIdx.x / NC) * GQ;
-    const int nq = (int)min((int64_t)GQ, a.count - q0);
     const int2 *gidx = (const int2 *)a.gidx;
     const int g0 = gidx[0].x;
     const int gn = min(GMAX, gidx[NAT - 1].x + gidx[NAT - 1].y - g0);   // lists are contiguous in (ma, mt)
@@ -201,39 +200,71 @@ __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
         s_lm[t] = ((const int2 *)a.glm)[g0 + t];
         s_g[t] = a.gg[g0 + t];
     }
-    if (tid < nq) s_off[tid] = a.out_off[a.order[a.start + q0 + tid]];
-    for (int t = tid; t < nq * YS; t += 256) {
-        const int ql = t / YS, r = t - ql * YS;
-        int nL = 0;
+    const int64_t ngroups = (a.count + GQ - 1) / GQ * NC;
+    // a group's Y values (NIT per thread) and output offsets are loaded into
+    // registers one group ahead: their loads are in flight while the previous
+    // group's rows are computed and stored
+    double yv[NIT];
+    int64_t offv = 0;
+    const auto load_group = [&](int64_t w) {
+        const int c = (int)(w % NC);
+        const int64_t q0 = w / NC * GQ;
+        const int nq = (int)min((int64_t)GQ, a.count - q0);
+        if (tid < nq) offv = a.out_off[a.order[a.start + q0 + tid]];
+        // the group's Y values sit in one window of Yv (c = 0) or Yd: a uniform
+        // base and 32-bit offsets (a triple's Y stride is YS)
+        const double *base = c == 0 ? a.Yv + q0 * YS : a.Yd + 3 * q0 * YS;
 #pragma unroll
-        for (int n = 1; n < NLA; ++n) nL += r >= loffc(n) ? 1 : 0;
-        const int L = LAMIN + 2 * nL;
-        const int64_t yb = (q0 + ql) * a.ys;
-        sY[t] = c == 0 ? a.Yv[yb + r] : a.Yd[3 * yb + 3 * loffc(nL) + (c - 1) * (2 * L + 1) * NB + (r - loffc(nL))];
-    }
-    __syncthreads();
-    // a thread takes one (triple, ma, mt) row: all NB values of mb at once, so
-    // each Gaunt term's coefficient and (L, M) are read once for NB products;
-    // consecutive threads write consecutive rows (contiguous stores)
-    for (int e = tid; e < nq * NAT; e += 256) {
-        const int ql = e / NAT, amt = e - ql * NAT;
-        const int2 se = s_idx[amt];
-        const double *y = sY + ql * YS;
-        double v[NB];
+        for (int it = 0; it < NIT; ++it) {
+            const int t = tid + it * 256;
+            if (t < nq * YS) {
+                const int ql = t / YS, r = t - ql * YS;
+                int nL = 0;
 #pragma unroll
-        for (int mb = 0; mb < NB; ++mb) v[mb] = 0.0;
-        for (int k = se.x; k < se.x + se.y && k < gn; ++k) {
-            const int L = s_lm[k].x, M = s_lm[k].y;
-            const double g = s_g[k];
-            const int n = (L - LAMIN) / 2;
-            const double *yl = y + NB * (n * (2 * LAMIN + 1) + 2 * n * (n - 1)) + (M + L) * NB;
-#pragma unroll
-            for (int mb = 0; mb < NB; ++mb) v[mb] = fma(g, yl[mb], v[mb]);
+                for (int n = 1; n < NLA; ++n) nL += r >= loffc(n) ? 1 : 0;
+                const int L = LAMIN + 2 * nL;
+                const int o = c == 0 ? t : 3 * ql * YS + 3 * loffc(nL) + (c - 1) * (2 * L + 1) * NB + (r - loffc(nL));
+                yv[it] = base[o];
+            }
         }
-        const int64_t off = s_off[ql];
-        double *dst = c == 0 ? a.out + off + amt * NB : a.dout + 3 * off + (int64_t)(c - 1) * SZ + amt * NB;
+    };
+    if (blockIdx.x < ngroups) load_group(blockIdx.x);
+    for (int64_t w = blockIdx.x; w < ngroups; w += gridDim.x) {
+        const int c = (int)(w % NC);
+        const int64_t q0 = w / NC * GQ;
+        const int nq = (int)min((int64_t)GQ, a.count - q0);
+        __syncthreads();   // the previous group's rows are written (and the lists staged)
+        if (tid < nq) s_off[tid] = offv;
 #pragma unroll
-        for (int mb = 0; mb < NB; ++mb) dst[mb] = v[mb];
+        for (int it = 0; it < NIT; ++it) {
+            const int t = tid + it * 256;
+            if (t < nq * YS) sY[t] = yv[it];
+        }
+        __syncthreads();
+        if (w + gridDim.x < ngroups) load_group(w + gridDim.x);
+        // a thread takes one (triple, ma, mt) row: all NB values of mb at once, so
+        // each Gaunt term's coefficient and (L, M) are read once for NB products;
+        // consecutive threads write consecutive rows (contiguous stores)
+        for (int e = tid; e < nq * NAT; e += 256) {
+            const int ql = e / NAT, amt = e - ql * NAT;
+            const int2 se = s_idx[amt];
+            const double *y = sY + ql * YS;
+            double v[NB];
+#pragma unroll
+            for (int mb = 0; mb < NB; ++mb) v[mb] = 0.0;
+            for (int k = se.x; k < se.x + se.y && k < gn; ++k) {
+                const int L = s_lm[k].x, M = s_lm[k].y;
+                const double g = s_g[k];
+                const int n = (L - LAMIN) / 2;
+                const double *yl = y + NB * (n * (2 * LAMIN + 1) + 2 * n * (n - 1)) + (M + L) * NB;
+#pragma unroll
+                for (int mb = 0; mb < NB; ++mb) v[mb] = fma(g, yl[mb], v[mb]);
+            }
+            const int64_t off = s_off[ql];
+            double *dst = c == 0 ? a.out + off + amt * NB : a.dout + 3 * off + (int64_t)(c - 1) * SZ + amt * NB;
+#pragma unroll
+            for (int mb = 0; mb < NB; ++mb) dst[mb] = v[mb];
+        }
     }
 }
 
@@ -418,8 +449,8 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
         GauntArgs ga{c->order, out_off, c->gaunt_idx + (size_t)(it.la * (AAB_LT + 1) + it.lt) * maxmm * 2,
                      c->gaunt_lm, c->gaunt_g, c->Yv[it.w], deriv ? c->Yd[it.w] : nullptr, out, dout, it.c0, it.cn,
                      it.ys, it.la, it.lt, it.lb, NC, it.lamin};
-        const int64_t groups = (it.cn + GQ - 1) / GQ;
-        gaunt_table()[it.key * 2 + D](sw, (unsigned)(groups * NC), ga);
+        const int64_t groups = (it.cn + GQ - 1) / GQ * NC;
+        gaunt_table()[it.key * 2 + D](sw, (unsigned)std::min<int64_t>(groups, GAUNT_GRID), ga);
         const hipError_t e = hipGetLastError();
         if (first == hipSuccess) first = e;
     }
