@@ -70,12 +70,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic():
+def stored_traffic(args):
     """HBM bytes per evaluation (the heavy- and light-class launches of k_persist<true>)
     on this workload from the committed rocprofv3 counter summary (FETCH_SIZE and
-    WRITE_SIZE, calibrated on a plain copy), or None when there is none or the
-    kernel sources changed since"""
-    if not os.path.exists(TRAFFIC_FILE):
+    WRITE_SIZE, calibrated on a plain copy), or None when there is none, the
+    kernel sources changed since, or the run is not the one the counters were
+    taken on (the full 256 molecules, round-robin tile order)"""
+    if args.n_mol != 256 or args.tile_order != "round-robin" or not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
     for line in open(TRAFFIC_FILE):
@@ -187,6 +188,9 @@ def main():
                     choices=["round-robin", "alternating", "heaviest-first", "auto"],
                     help="tile order of the plans' persistent queue (auto: timed by the plan autotuner)")
     ap.add_argument("--no-extra", action="store_true", help="skip the measurements of the other workloads")
+    ap.add_argument("--extras", default="all",
+                    help="comma list of the other workloads to measure: overlap200, five_ops500, aab2000, "
+                         "molopt_sets, screen5000 (default all)")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB first (calibrates HBM byte counters)")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the copy / FP64 ceiling measurement")
@@ -303,7 +307,7 @@ def main():
     gbs = b_launch / (ms_launch / 1e3) / 1e9
     tfl = f_launch / (ms_launch / 1e3) / 1e12
     roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(),
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(args),
                 "kernel": "shg::k_persist<true, heavy> + shg::k_persist<true, light> (one evaluation: the "
                           "heavy-class and the light-class persistent launches of a plan)",
                 "avg_launch_ms": round(ms_launch, 4),
@@ -470,168 +474,177 @@ def run_extras(args, eng, shg, inputs, workmodel, np, torch):
     dev = torch.device("cuda")
     extra = {}
     steps = max(3, args.steps // 2)
+    sel = None if args.extras == "all" else set(args.extras.split(","))
+
+    def want(name):
+        return sel is None or name in sel
 
     # ---- 200 isolated overlap pairs: launch latency, single call vs graph replay ----
-    log("extra: overlap200 latency")
-    w1 = inputs.overlap200()
-    dsh1, p1, oo1, _, tot1 = upload(eng, w1)
-    o1 = torch.empty(tot1, dtype=torch.float64, device=dev)
-    ms_single, _ = timed(eng, lambda: eng.pairs(dsh1, "overlap", 0.0, p1, oo1, o1), 50, 5)
-    pl1 = shg.Plan(eng, dsh1, "overlap", 0.0, p1, oo1, o1, None, shg.PLAN_PERSISTENT)
-    ms_graph, _ = timed(eng, pl1.execute, 200, 10)
-    pl1.close()
-    extra["overlap200"] = {"workload": "200 isolated atom pairs, one shell per center, l 0..2, K 3, overlap values",
-                           "blocks": len(w1.pairs),
-                           "single_call_us": round(ms_single * 1e3, 2),
-                           "single_call_blocks_per_s": round(len(w1.pairs) / (ms_single / 1e3), 1),
-                           "graph_replay_us": round(ms_graph * 1e3, 2),
-                           "graph_replay_blocks_per_s": round(len(w1.pairs) / (ms_graph / 1e3), 1),
-                           "note": "latency bound: shg_pairs bins and synchronises once per call; a plan replays "
-                                   "its graphs with no host synchronisation"}
+    if want("overlap200"):
+        log("extra: overlap200 latency")
+        w1 = inputs.overlap200()
+        dsh1, p1, oo1, _, tot1 = upload(eng, w1)
+        o1 = torch.empty(tot1, dtype=torch.float64, device=dev)
+        ms_single, _ = timed(eng, lambda: eng.pairs(dsh1, "overlap", 0.0, p1, oo1, o1), 50, 5)
+        pl1 = shg.Plan(eng, dsh1, "overlap", 0.0, p1, oo1, o1, None, shg.PLAN_PERSISTENT)
+        ms_graph, _ = timed(eng, pl1.execute, 200, 10)
+        pl1.close()
+        extra["overlap200"] = {"workload": "200 isolated atom pairs, one shell per center, l 0..2, K 3, overlap values",
+                               "blocks": len(w1.pairs),
+                               "single_call_us": round(ms_single * 1e3, 2),
+                               "single_call_blocks_per_s": round(len(w1.pairs) / (ms_single / 1e3), 1),
+                               "graph_replay_us": round(ms_graph * 1e3, 2),
+                               "graph_replay_blocks_per_s": round(len(w1.pairs) / (ms_graph / 1e3), 1),
+                               "note": "latency bound: shg_pairs bins and synchronises once per call; a plan replays "
+                                       "its graphs with no host synchronisation"}
 
     # ---- the 500-atom five-operator workload ----
-    log("extra: five_ops500")
-    w2 = inputs.five_ops500()
-    dsh2, p2, oo2, off2, tot2 = upload(eng, w2)
-    ops = list(inputs.FIVE_OPS)
-    n2 = len(w2.pairs)
-    o2 = {op: torch.empty(tot2, dtype=torch.float64, device=dev) for op in ops}
-    d2 = {op: torch.empty(3 * tot2, dtype=torch.float64, device=dev) for op in ops}
-    ms_p2, _ = timed(eng, lambda: [eng.pairs(dsh2, op, w2.omega[op], p2, oo2, o2[op], d2[op]) for op in ops],
-                     steps, 2)
-    tau2 = 1e-10 / (n2 * 5)
-    sp2 = make_plans(shg, eng, dsh2, ops, w2.omega, p2, oo2, o2, d2, args.tile_order, tau=tau2)
-    ms_s2, _ = timed(eng, lambda: [p.execute() for p in sp2], steps, 2)
-    for p in sp2:
-        p.close()
-    extra["five_ops500"] = {"workload": "500 atoms, 20 bohr cube, 4 shells/atom l 0..4 K 1..7, ordered atom pairs "
-                                        "within 12 bohr, 5 operators, values + d/dR_a",
-                            "pairs": n2, "blocks_per_step": n2 * 5,
-                            "plain_blocks_per_s": round(n2 * 5 / (ms_p2 / 1e3), 1),
-                            "batched_screened_blocks_per_s": round(n2 * 5 / (ms_s2 / 1e3), 1),
-                            "speedup": round(ms_p2 / ms_s2, 3)}
-    # swap symmetry on this ordered list: screened plans over a <= b, (b, a) by transposition
-    a_, b_ = w2.pairs[:, 0].astype(np.int64), w2.pairs[:, 1].astype(np.int64)
-    nsh = int(w2.shells.n)
-    key = a_ * nsh + b_
-    kord = np.argsort(key)
-    mir = np.nonzero(a_ > b_)[0]
-    pos = np.minimum(np.searchsorted(key[kord], b_[mir] * nsh + a_[mir]), n2 - 1)
-    partner = kord[pos]
-    if len(mir) and np.all(key[partner] == b_[mir] * nsh + a_[mir]):
-        ci = np.nonzero(a_ <= b_)[0]
-        cp = torch.as_tensor(np.ascontiguousarray(w2.pairs[ci], np.int32), device=dev)
-        coff = torch.as_tensor(off2[ci], device=dev)
-        sw_p = torch.as_tensor(np.ascontiguousarray(w2.pairs[partner], np.int32), device=dev)
-        sw_src = torch.as_tensor(off2[partner], device=dev)
-        sw_dst = torch.as_tensor(off2[mir], device=dev)
-        xo = {op: torch.zeros(tot2, dtype=torch.float64, device=dev) for op in ops}
-        xd = {op: torch.zeros(3 * tot2, dtype=torch.float64, device=dev) for op in ops}
-        xp = make_plans(shg, eng, dsh2, ops, w2.omega, cp, coff, xo, xd, args.tile_order, tau=tau2)
-
-        def step_swap():
-            for op, p in zip(ops, xp):
-                p.execute()
-                eng.pairs_swap(dsh2, sw_p, sw_src, sw_dst, xo[op], xd[op])
-
-        step_swap()
-        eng._check(eng.lib.shg_pairs_swap_check(eng.ctx))
-        ms_x, _ = timed(eng, step_swap, steps, 2)
-        xbad = 0
-        for op in ops:
-            for x_, r_ in ((xo[op], o2[op]), (xd[op], d2[op])):
-                tol = 1e-12 * r_.abs() + 1e-14 * max(1.0, r_.abs().max().item())
-                xbad += int((((x_ - r_).abs() > tol) & (x_ != 0)).sum().item())
-        for p in xp:
+    if want("five_ops500"):
+        log("extra: five_ops500")
+        w2 = inputs.five_ops500()
+        dsh2, p2, oo2, off2, tot2 = upload(eng, w2)
+        ops = list(inputs.FIVE_OPS)
+        n2 = len(w2.pairs)
+        o2 = {op: torch.empty(tot2, dtype=torch.float64, device=dev) for op in ops}
+        d2 = {op: torch.empty(3 * tot2, dtype=torch.float64, device=dev) for op in ops}
+        ms_p2, _ = timed(eng, lambda: [eng.pairs(dsh2, op, w2.omega[op], p2, oo2, o2[op], d2[op]) for op in ops],
+                         steps, 2)
+        tau2 = 1e-10 / (n2 * 5)
+        sp2 = make_plans(shg, eng, dsh2, ops, w2.omega, p2, oo2, o2, d2, args.tile_order, tau=tau2)
+        ms_s2, _ = timed(eng, lambda: [p.execute() for p in sp2], steps, 2)
+        for p in sp2:
             p.close()
-        extra["five_ops500"]["screened_swap_blocks_per_s"] = round(n2 * 5 / (ms_x / 1e3), 1)
-        extra["five_ops500"]["swap_within_tol"] = xbad == 0
-        del xo, xd
-    # next-row operators on the same pair list
-    b_r2n = int(workmodel.workload_bytes(w2, True))
-    r2n = {"pairs": n2, "alg_bytes_per_call": b_r2n}
-    for nr in (1, 3, 5):
-        ms5, _ = timed(eng, lambda: eng.pairs_r2n(dsh2, nr, p2, oo2, o2[ops[0]], d2[ops[0]]), steps, 1)
-        r2n[f"n{nr}"] = {"ms_per_call": round(ms5, 4), "blocks_per_s": round(n2 / (ms5 / 1e3), 1),
-                         "hbm_frac": round(b_r2n / (ms5 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
-    extra["r2n_five_ops500"] = r2n
-    ms6, _ = timed(eng, lambda: eng.pairs(dsh2, "gcoulomb", 0.7, p2, oo2, o2[ops[0]], d2[ops[0]]), steps, 1)
-    extra["gcoulomb_five_ops500"] = {"ms_per_call": round(ms6, 4), "blocks_per_s": round(n2 / (ms6 / 1e3), 1),
-                                     "hbm_frac": round(b_r2n / (ms6 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
-    del o2, d2
-    torch.cuda.empty_cache()
+        extra["five_ops500"] = {"workload": "500 atoms, 20 bohr cube, 4 shells/atom l 0..4 K 1..7, ordered atom pairs "
+                                            "within 12 bohr, 5 operators, values + d/dR_a",
+                                "pairs": n2, "blocks_per_step": n2 * 5,
+                                "plain_blocks_per_s": round(n2 * 5 / (ms_p2 / 1e3), 1),
+                                "batched_screened_blocks_per_s": round(n2 * 5 / (ms_s2 / 1e3), 1),
+                                "speedup": round(ms_p2 / ms_s2, 3)}
+        # swap symmetry on this ordered list: screened plans over a <= b, (b, a) by transposition
+        a_, b_ = w2.pairs[:, 0].astype(np.int64), w2.pairs[:, 1].astype(np.int64)
+        nsh = int(w2.shells.n)
+        key = a_ * nsh + b_
+        kord = np.argsort(key)
+        mir = np.nonzero(a_ > b_)[0]
+        pos = np.minimum(np.searchsorted(key[kord], b_[mir] * nsh + a_[mir]), n2 - 1)
+        partner = kord[pos]
+        if len(mir) and np.all(key[partner] == b_[mir] * nsh + a_[mir]):
+            ci = np.nonzero(a_ <= b_)[0]
+            cp = torch.as_tensor(np.ascontiguousarray(w2.pairs[ci], np.int32), device=dev)
+            coff = torch.as_tensor(off2[ci], device=dev)
+            sw_p = torch.as_tensor(np.ascontiguousarray(w2.pairs[partner], np.int32), device=dev)
+            sw_src = torch.as_tensor(off2[partner], device=dev)
+            sw_dst = torch.as_tensor(off2[mir], device=dev)
+            xo = {op: torch.zeros(tot2, dtype=torch.float64, device=dev) for op in ops}
+            xd = {op: torch.zeros(3 * tot2, dtype=torch.float64, device=dev) for op in ops}
+            xp = make_plans(shg, eng, dsh2, ops, w2.omega, cp, coff, xo, xd, args.tile_order, tau=tau2)
+
+            def step_swap():
+                for op, p in zip(ops, xp):
+                    p.execute()
+                    eng.pairs_swap(dsh2, sw_p, sw_src, sw_dst, xo[op], xd[op])
+
+            step_swap()
+            eng._check(eng.lib.shg_pairs_swap_check(eng.ctx))
+            ms_x, _ = timed(eng, step_swap, steps, 2)
+            xbad = 0
+            for op in ops:
+                for x_, r_ in ((xo[op], o2[op]), (xd[op], d2[op])):
+                    tol = 1e-12 * r_.abs() + 1e-14 * max(1.0, r_.abs().max().item())
+                    xbad += int((((x_ - r_).abs() > tol) & (x_ != 0)).sum().item())
+            for p in xp:
+                p.close()
+            extra["five_ops500"]["screened_swap_blocks_per_s"] = round(n2 * 5 / (ms_x / 1e3), 1)
+            extra["five_ops500"]["swap_within_tol"] = xbad == 0
+            del xo, xd
+        # next-row operators on the same pair list
+        b_r2n = int(workmodel.workload_bytes(w2, True))
+        r2n = {"pairs": n2, "alg_bytes_per_call": b_r2n}
+        for nr in (1, 3, 5):
+            ms5, _ = timed(eng, lambda: eng.pairs_r2n(dsh2, nr, p2, oo2, o2[ops[0]], d2[ops[0]]), steps, 1)
+            r2n[f"n{nr}"] = {"ms_per_call": round(ms5, 4), "blocks_per_s": round(n2 / (ms5 / 1e3), 1),
+                             "hbm_frac": round(b_r2n / (ms5 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        extra["r2n_five_ops500"] = r2n
+        ms6, _ = timed(eng, lambda: eng.pairs(dsh2, "gcoulomb", 0.7, p2, oo2, o2[ops[0]], d2[ops[0]]), steps, 1)
+        extra["gcoulomb_five_ops500"] = {"ms_per_call": round(ms6, 4), "blocks_per_s": round(n2 / (ms6 / 1e3), 1),
+                                         "hbm_frac": round(b_r2n / (ms6 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del o2, d2
+        torch.cuda.empty_cache()
 
     # ---- three-index overlap, full 2000-atom RI workload, one call ----
-    log("extra: aab2000 full size")
-    w3 = inputs.aab2000()
-    off3, tot3 = w3.out_offsets()
-    orb3, aux3 = eng.shells(w3.shells), eng.shells(w3.aux)
-    tri3 = torch.as_tensor(np.ascontiguousarray(w3.triples, np.int32), device=dev)
-    oo3 = torch.as_tensor(off3, device=dev)
-    o3 = torch.empty(tot3, dtype=torch.float64, device=dev)
-    d3 = torch.empty(3 * tot3, dtype=torch.float64, device=dev)
-    nt3 = len(w3.triples)
-    sz = w3.shells.l
-    b3 = int(workmodel.triple_bytes(sz[w3.triples[:, 0]], w3.aux.l[w3.triples[:, 1]], sz[w3.triples[:, 2]],
-                                    True).sum())
-    ms3, _ = timed(eng, lambda: eng.aab(orb3, aux3, tri3, oo3, o3, d3), 3, 1)
-    finite = bool(torch.isfinite(o3).all().item()) and bool(torch.isfinite(d3).all().item())
-    extra["aab2000"] = {"workload": "2000 atoms, 40 bohr cube, orbital l 0..3 K 5, RI l 0..6 uncontracted, "
-                                    "triples (orbital on X, RI on X, orbital on Y) of ordered atom pairs within "
-                                    "10 bohr, values + d/dR_A, full size in one shg_aab call",
-                        "triples": nt3, "output_gb": round(4 * tot3 * 8 / 1e9, 2), "ms_per_call": round(ms3, 3),
-                        "triples_per_s": round(nt3 / (ms3 / 1e3), 1), "alg_bytes_per_call": b3,
-                        "hbm_gbs": round(b3 / (ms3 / 1e3) / 1e9, 1),
-                        "hbm_frac": round(b3 / (ms3 / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "all_finite": finite}
-    del o3, d3, tri3, oo3
-    torch.cuda.empty_cache()
+    if want("aab2000"):
+        log("extra: aab2000 full size")
+        w3 = inputs.aab2000()
+        off3, tot3 = w3.out_offsets()
+        orb3, aux3 = eng.shells(w3.shells), eng.shells(w3.aux)
+        tri3 = torch.as_tensor(np.ascontiguousarray(w3.triples, np.int32), device=dev)
+        oo3 = torch.as_tensor(off3, device=dev)
+        o3 = torch.empty(tot3, dtype=torch.float64, device=dev)
+        d3 = torch.empty(3 * tot3, dtype=torch.float64, device=dev)
+        nt3 = len(w3.triples)
+        sz = w3.shells.l
+        b3 = int(workmodel.triple_bytes(sz[w3.triples[:, 0]], w3.aux.l[w3.triples[:, 1]], sz[w3.triples[:, 2]],
+                                        True).sum())
+        ms3, _ = timed(eng, lambda: eng.aab(orb3, aux3, tri3, oo3, o3, d3), 3, 1)
+        finite = bool(torch.isfinite(o3).all().item()) and bool(torch.isfinite(d3).all().item())
+        extra["aab2000"] = {"workload": "2000 atoms, 40 bohr cube, orbital l 0..3 K 5, RI l 0..6 uncontracted, "
+                                        "triples (orbital on X, RI on X, orbital on Y) of ordered atom pairs within "
+                                        "10 bohr, values + d/dR_A, full size in one shg_aab call",
+                            "triples": nt3, "output_gb": round(4 * tot3 * 8 / 1e9, 2), "ms_per_call": round(ms3, 3),
+                            "triples_per_s": round(nt3 / (ms3 / 1e3), 1), "alg_bytes_per_call": b3,
+                            "hbm_gbs": round(b3 / (ms3 / 1e3) / 1e9, 1),
+                            "hbm_frac": round(b3 / (ms3 / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "all_finite": finite}
+        del o3, d3, tri3, oo3
+        torch.cuda.empty_cache()
 
     # ---- family sets on the paper's MOLOPT data: set path vs the same functions as shells ----
-    log("extra: MOLOPT family sets")
-    extra["molopt_sets"] = {}
-    for name, natoms, dens, kinds, cut in (("water", 12000, 0.0148, ("O-DZVP", "H-DZVP", "H-DZVP"), 10.0),
-                                           ("copper", 4000, 0.0126, ("Cu-DZVP",), 9.0)):
-        extra["molopt_sets"][name] = family_set_extra(eng, shg, inputs, np, torch, natoms, dens, kinds, cut, steps)
+    if want("molopt_sets"):
+        log("extra: MOLOPT family sets")
+        extra["molopt_sets"] = {}
+        for name, natoms, dens, kinds, cut in (("water", 12000, 0.0148, ("O-DZVP", "H-DZVP", "H-DZVP"), 10.0),
+                                               ("copper", 4000, 0.0126, ("Cu-DZVP",), 9.0)):
+            extra["molopt_sets"][name] = family_set_extra(eng, shg, inputs, np, torch, natoms, dens, kinds, cut, steps)
 
     # ---- 5000-atom screening workload: bound vs bound + trained network at the budget ----
-    from paper_1701_06588_amd import screen
-    if os.path.exists(screen.MODEL):
-        log("extra: screen5000 ablation")
-        w5 = inputs.screen5000()
-        dsh5, p5, oo5, off5, tot5 = upload(eng, w5)
-        n5 = len(w5.pairs)
-        ops5 = list(w5.ops)
-        ncand = n5 * len(ops5)
-        tau5 = 1e-10 / ncand
-        ref5 = torch.empty(tot5, dtype=torch.float64, device=dev)
-        got5 = torch.empty(tot5, dtype=torch.float64, device=dev)
-        mlp = shg.Mlp(eng, 0)
-        mlp.load(screen.MODEL)
-        abl = {"workload": "5000 atoms, 60 bohr cube, basis as the 500-atom workload, ordered atom pairs within "
-                           "12 bohr, Coulomb and erfc values", "pairs": n5, "candidates": ncand, "tau_blk": tau5,
-               "variants": {}}
-        for op in ops5:
-            ms_pl, _ = timed(eng, lambda: eng.pairs(dsh5, op, w5.omega[op], p5, oo5, ref5), 3, 1)
-            abl["variants"].setdefault("plain", {})[op] = {"ms": round(ms_pl, 4)}
-            for vname, model, fl in (("bound", None, 0), ("bound+mlp", mlp, 0),
-                                     ("bound, compacting stage", None, shg.PLAN_COMPACT)):
-                pl = shg.Plan(eng, dsh5, op, w5.omega[op], p5, oo5, got5, None, shg.PLAN_PERSISTENT | fl, tau=tau5,
-                              mlp=model)
-                # (a compacting plan builds its queue on the device, in the first two orders only)
-                order = args.tile_order if args.tile_order != "auto" else "round-robin"
-                pl.set_tile_order("alternating" if fl and order == "round-robin" else order)
-                ms_v, _ = timed(eng, pl.execute, 3, 1)
-                bad5, mass5 = compare_chunked(got5, ref5)
-                abl["variants"].setdefault(vname, {})[op] = {
-                    "ms": round(ms_v, 4), "skipped": int(pl.skipped().size), "missed_mass": mass5,
-                    "kept_bitwise_equal": bad5 == 0}
-                pl.close()
-        for d in abl["variants"].values():
-            d["blocks_per_s"] = round(ncand / (sum(v["ms"] for v in d.values()) / 1e3), 1)
-        mlp.close()
-        extra["screen5000_ablation"] = abl
-        del ref5, got5
-        torch.cuda.empty_cache()
+    if want("screen5000"):
+        from paper_1701_06588_amd import screen
+        if os.path.exists(screen.MODEL):
+            log("extra: screen5000 ablation")
+            w5 = inputs.screen5000()
+            dsh5, p5, oo5, off5, tot5 = upload(eng, w5)
+            n5 = len(w5.pairs)
+            ops5 = list(w5.ops)
+            ncand = n5 * len(ops5)
+            tau5 = 1e-10 / ncand
+            ref5 = torch.empty(tot5, dtype=torch.float64, device=dev)
+            got5 = torch.empty(tot5, dtype=torch.float64, device=dev)
+            mlp = shg.Mlp(eng, 0)
+            mlp.load(screen.MODEL)
+            abl = {"workload": "5000 atoms, 60 bohr cube, basis as the 500-atom workload, ordered atom pairs within "
+                               "12 bohr, Coulomb and erfc values", "pairs": n5, "candidates": ncand, "tau_blk": tau5,
+                   "variants": {}}
+            for op in ops5:
+                ms_pl, _ = timed(eng, lambda: eng.pairs(dsh5, op, w5.omega[op], p5, oo5, ref5), 3, 1)
+                abl["variants"].setdefault("plain", {})[op] = {"ms": round(ms_pl, 4)}
+                for vname, model, fl in (("bound", None, 0), ("bound+mlp", mlp, 0),
+                                         ("bound, compacting stage", None, shg.PLAN_COMPACT)):
+                    pl = shg.Plan(eng, dsh5, op, w5.omega[op], p5, oo5, got5, None, shg.PLAN_PERSISTENT | fl, tau=tau5,
+                                  mlp=model)
+                    # (a compacting plan builds its queue on the device, in the first two orders only)
+                    order = args.tile_order if args.tile_order != "auto" else "round-robin"
+                    pl.set_tile_order("alternating" if fl and order == "round-robin" else order)
+                    ms_v, _ = timed(eng, pl.execute, 3, 1)
+                    bad5, mass5 = compare_chunked(got5, ref5)
+                    abl["variants"].setdefault(vname, {})[op] = {
+                        "ms": round(ms_v, 4), "skipped": int(pl.skipped().size), "missed_mass": mass5,
+                        "kept_bitwise_equal": bad5 == 0}
+                    pl.close()
+            for d in abl["variants"].values():
+                d["blocks_per_s"] = round(ncand / (sum(v["ms"] for v in d.values()) / 1e3), 1)
+            mlp.close()
+            extra["screen5000_ablation"] = abl
+            del ref5, got5
+            torch.cuda.empty_cache()
     return extra
 
 
