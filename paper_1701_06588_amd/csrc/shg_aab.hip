@@ -165,13 +165,13 @@ struct GauntArgs {
     int la, lt, lb, nc, lamin;
 };
 
-// A group is GQ triples and one component (value or one of x, y, z). Each
-// workgroup stages the class's Gaunt lists (at most 2 terms per L_a value) in
-// LDS once and then takes groups blockIdx.x, blockIdx.x + gridDim.x, ...: it
-// stages the group's Y blocks (every L_a of the class, coalesced reads) and
-// computes out[ma][mt][mb] = sum over the list of (ma, mt) of G * Y_L[M][mb], a
-// thread per (triple, ma, mt) row of NB values. The class is a template
-// parameter so that all index arithmetic is by constants.
+// A group is GQ triples; a pass is one group and one component (value or one
+// of x, y, z). Each workgroup stages the class's Gaunt lists (at most 2 terms
+// per L_a value) in LDS once and then runs passes: it stages the pass's Y
+// blocks (every L_a of the class) and computes out[ma][mt][mb] = sum over the
+// list of (ma, mt) of G * Y_L[M][mb], a thread per (triple, ma, mt) row of NB
+// values. The class is a template parameter so that all index arithmetic is by
+// constants.
 constexpr int GQ = 8;
 constexpr int GAUNT_GRID = 2048;   // workgroups per launch at most (eight per CU)
 
@@ -200,15 +200,19 @@ __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
         s_lm[t] = ((const int2 *)a.glm)[g0 + t];
         s_g[t] = a.gg[g0 + t];
     }
-    const int64_t ngroups = (a.count + GQ - 1) / GQ * NC;
-    // a group's Y values (NIT per thread) and output offsets are loaded into
-    // registers one group ahead: their loads are in flight while the previous
-    // group's rows are computed and stored
+    // a workgroup takes groups blockIdx.x, blockIdx.x + gridDim.x, ... and runs
+    // the NC components of each group as consecutive passes: the derivative
+    // components of a Y row are adjacent segments that share cache lines at
+    // their edges, so a line fetched for one pass is still in this CU's L2 for
+    // the next, and the group's output rows are written from one XCD
+    const int64_t ngt = (a.count + GQ - 1) / GQ;
+    // a pass's Y values (NIT per thread) and output offsets are loaded into
+    // registers one pass ahead: their loads are in flight while the previous
+    // pass's rows are computed and stored
     double yv[NIT];
     int64_t offv = 0;
-    const auto load_group = [&](int64_t w) {
-        const int c = (int)(w % NC);
-        const int64_t q0 = w / NC * GQ;
+    const auto load_pass = [&](int64_t g, int c) {
+        const int64_t q0 = g * GQ;
         const int nq = (int)min((int64_t)GQ, a.count - q0);
         if (tid < nq) offv = a.out_off[a.order[a.start + q0 + tid]];
         // the group's Y values sit in one window of Yv (c = 0) or Yd: a uniform
@@ -228,12 +232,13 @@ __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
             }
         }
     };
-    if (blockIdx.x < ngroups) load_group(blockIdx.x);
-    for (int64_t w = blockIdx.x; w < ngroups; w += gridDim.x) {
-        const int c = (int)(w % NC);
-        const int64_t q0 = w / NC * GQ;
+    int64_t g = blockIdx.x;
+    int c = 0;
+    if (g < ngt) load_pass(g, 0);
+    while (g < ngt) {
+        const int64_t q0 = g * GQ;
         const int nq = (int)min((int64_t)GQ, a.count - q0);
-        __syncthreads();   // the previous group's rows are written (and the lists staged)
+        __syncthreads();   // the previous pass's rows are written (and the lists staged)
         if (tid < nq) s_off[tid] = offv;
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
@@ -241,7 +246,13 @@ __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
             if (t < nq * YS) sY[t] = yv[it];
         }
         __syncthreads();
-        if (w + gridDim.x < ngroups) load_group(w + gridDim.x);
+        int64_t gnext = g;
+        int cnext = c + 1;
+        if (cnext == NC) {
+            cnext = 0;
+            gnext += gridDim.x;
+        }
+        if (gnext < ngt) load_pass(gnext, cnext);
         // a thread takes one (triple, ma, mt) row: all NB values of mb at once, so
         // each Gaunt term's coefficient and (L, M) are read once for NB products;
         // consecutive threads write consecutive rows (contiguous stores)
@@ -265,6 +276,8 @@ __global__ __launch_bounds__(256) void k_aab_gaunt(GauntArgs a)
 #pragma unroll
             for (int mb = 0; mb < NB; ++mb) dst[mb] = v[mb];
         }
+        g = gnext;
+        c = cnext;
     }
 }
 
@@ -449,7 +462,7 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
         GauntArgs ga{c->order, out_off, c->gaunt_idx + (size_t)(it.la * (AAB_LT + 1) + it.lt) * maxmm * 2,
                      c->gaunt_lm, c->gaunt_g, c->Yv[it.w], deriv ? c->Yd[it.w] : nullptr, out, dout, it.c0, it.cn,
                      it.ys, it.la, it.lt, it.lb, NC, it.lamin};
-        const int64_t groups = (it.cn + GQ - 1) / GQ * NC;
+        const int64_t groups = (it.cn + GQ - 1) / GQ;
         gaunt_table()[it.key * 2 + D](sw, (unsigned)std::min<int64_t>(groups, GAUNT_GRID), ga);
         const hipError_t e = hipGetLastError();
         if (first == hipSuccess) first = e;
