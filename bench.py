@@ -110,6 +110,18 @@ def timed(eng, fn, steps, warmup):
     return t0.elapsed_time(t1) / steps, wall
 
 
+def oracle_rate(fn, units, unit, sample, reps=1):
+    """the CPU oracle's rate on a bounded sample: fn() evaluates `units` blocks
+    (or triples) on all host threads; reps calls are timed together"""
+    import oracle
+    c0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    dt = time.perf_counter() - c0
+    return {"value": round(units * reps / dt, 1), "unit": unit, "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{sample}, {dt:.2f} s"}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -497,6 +509,11 @@ def run_extras(args, eng, shg, inputs, workmodel, np, torch):
                                "graph_replay_blocks_per_s": round(len(w1.pairs) / (ms_graph / 1e3), 1),
                                "note": "latency bound: shg_pairs bins and synchronises once per call; a plan replays "
                                        "its graphs with no host synchronisation"}
+        if args.cpu_sample > 0:
+            import oracle
+            extra["overlap200"]["cpu_oracle"] = oracle_rate(
+                lambda: oracle.pairs(w1.shells, "overlap", 0.0, w1.pairs), len(w1.pairs), "blocks/s",
+                "all 200 pairs, overlap values, 50 repetitions", reps=50)
 
     # ---- the 500-atom five-operator workload ----
     if want("five_ops500"):
@@ -520,6 +537,12 @@ def run_extras(args, eng, shg, inputs, workmodel, np, torch):
                                 "plain_blocks_per_s": round(n2 * 5 / (ms_p2 / 1e3), 1),
                                 "batched_screened_blocks_per_s": round(n2 * 5 / (ms_s2 / 1e3), 1),
                                 "speedup": round(ms_p2 / ms_s2, 3)}
+        if args.cpu_sample > 0:
+            import oracle
+            i2 = np.sort(np.random.default_rng(0).choice(n2, min(20000, n2), replace=False))
+            extra["five_ops500"]["cpu_oracle"] = oracle_rate(
+                lambda: [oracle.pairs(w2.shells, op, w2.omega[op], w2.pairs[i2], deriv=True) for op in ops],
+                len(i2) * len(ops), "blocks/s", f"{len(i2)} random pairs x 5 operators, values + d/dR_a")
         # swap symmetry on this ordered list: screened plans over a <= b, (b, a) by transposition
         a_, b_ = w2.pairs[:, 0].astype(np.int64), w2.pairs[:, 1].astype(np.int64)
         nsh = int(w2.shells.n)
@@ -594,6 +617,12 @@ def run_extras(args, eng, shg, inputs, workmodel, np, torch):
                             "triples_per_s": round(nt3 / (ms3 / 1e3), 1), "alg_bytes_per_call": b3,
                             "hbm_gbs": round(b3 / (ms3 / 1e3) / 1e9, 1),
                             "hbm_frac": round(b3 / (ms3 / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "all_finite": finite}
+        if args.cpu_sample > 0:
+            import oracle
+            i3 = np.sort(np.random.default_rng(0).choice(nt3, min(5000, nt3), replace=False))
+            extra["aab2000"]["cpu_oracle"] = oracle_rate(
+                lambda: oracle.aab(w3.shells, w3.aux, w3.triples[i3], deriv=True), len(i3), "triples/s",
+                f"{len(i3)} random triples, values + d/dR_A")
         del o3, d3, tri3, oo3
         torch.cuda.empty_cache()
 
@@ -642,6 +671,12 @@ def run_extras(args, eng, shg, inputs, workmodel, np, torch):
             for d in abl["variants"].values():
                 d["blocks_per_s"] = round(ncand / (sum(v["ms"] for v in d.values()) / 1e3), 1)
             mlp.close()
+            if args.cpu_sample > 0:
+                import oracle
+                i5 = np.sort(np.random.default_rng(0).choice(n5, min(20000, n5), replace=False))
+                abl["cpu_oracle"] = oracle_rate(
+                    lambda: [oracle.pairs(w5.shells, op, w5.omega[op], w5.pairs[i5]) for op in ops5],
+                    len(i5) * len(ops5), "blocks/s", f"{len(i5)} random pairs x {len(ops5)} operators, values")
             extra["screen5000_ablation"] = abl
             del ref5, got5
             torch.cuda.empty_cache()
