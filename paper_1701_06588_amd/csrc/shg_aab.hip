@@ -29,7 +29,7 @@ namespace {
 
 constexpr int AAB_LA = 3, AAB_LT = 6, AAB_LB = 3;
 constexpr int AAB_NCLASS = (AAB_LA + 1) * (AAB_LT + 1) * (AAB_LB + 1);
-constexpr int AAB_PSTRIDE = 32;
+constexpr int AAB_PSTRIDE = 32;   // radial-term doubles per triple: at most 4 L_a values x 8 orders
 constexpr int RAD_G = 8, RAD_TPB = 256;
 
 __device__ __forceinline__ int aab_key(int la, int lt, int lb) { return (la * (AAB_LT + 1) + lt) * (AAB_LB + 1) + lb; }
@@ -77,7 +77,7 @@ struct AabRadArgs {
     const int32_t *xnp;
     const int64_t *xoff;
     const double *xexp, *xw;     // auxiliary exponents and weights
-    double *P;                   // [pos - pbase][AAB_PSTRIDE]
+    double *P;                   // [L_a index][pos - pbase][8]: each L_a tile reads one contiguous slab
     int64_t pbase, start, count;
 };
 
@@ -122,11 +122,12 @@ __global__ __launch_bounds__(RAD_TPB) void k_aab_radial(AabRadArgs a)
 #pragma unroll
             for (int k = 0; k < 8; ++k) P[i][k] += __shfl_xor(P[i][k], m, RAD_G);
     if (live && g == 0) {
-        double *dst = a.P + (pos - a.pbase) * AAB_PSTRIDE;
 #pragma unroll
-        for (int i = 0; i < AK::NLA; ++i)
+        for (int i = 0; i < AK::NLA; ++i) {
+            double *dst = a.P + ((int64_t)i * a.count + (pos - a.pbase)) * 8;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) dst[i * 8 + k] = P[i][k];
+            for (int k = 0; k < 8; ++k) dst[k] = P[i][k];
+        }
     }
 }
 
@@ -450,8 +451,8 @@ extern "C" int shg_aab(shg_ctx *c, const shg_shells *orb, const shg_shells *aux,
             ta.triples = triples;
             ta.tstride = 3;
             ta.P = c->Pbuf[it.w];
-            ta.pstride = AAB_PSTRIDE;
-            ta.poff = iL * 8;
+            ta.pstride = 8;                    // P is [L_a index][triple][8]
+            ta.poff = (int)(iL * 8 * it.cn);
             ta.ybase = it.c0;
             ta.ys = it.ys;
             ta.yoff = loff;
