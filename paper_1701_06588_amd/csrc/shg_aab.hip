@@ -104,16 +104,39 @@ __global__ __launch_bounds__(RAD_TPB) void k_aab_radial(AabRadArgs a)
     for (int i = 0; i < AK::NLA; ++i)
 #pragma unroll
         for (int k = 0; k < 8; ++k) P[i][k] = 0.0;
+    // the triple's primitive data staged once in LDS (lane g loads primitive g of
+    // each shell, K <= KMAX < RAD_G, all loads independent): exponents, and the
+    // weights with the a and a~ weights' (2 alpha)^l factors taken out
+    __shared__ double sE[3][RAD_TPB / RAD_G][KMAX], sW[3][RAD_TPB / RAD_G][KMAX];
+    static_assert(KMAX <= RAD_G, "one primitive per lane");
+    const int ls = threadIdx.x / RAD_G;
+    if (live) {
+        if (g < ka) {
+            const double e = a.oexp[oa + g];
+            double f = a.ow[oa + g];
+#pragma unroll
+            for (int k = 0; k < LA; ++k) f *= 2.0 * e;
+            sE[0][ls][g] = e;
+            sW[0][ls][g] = f;
+        }
+        if (g < kt) {
+            const double e = a.xexp[ot + g];
+            double f = a.xw[ot + g];
+#pragma unroll
+            for (int k = 0; k < LT; ++k) f *= 2.0 * e;
+            sE[1][ls][g] = e;
+            sW[1][ls][g] = f;
+        }
+        if (g < kb) {
+            sE[2][ls][g] = a.oexp[ob + g];
+            sW[2][ls][g] = a.ow[ob + g];
+        }
+    }
+    __syncthreads();
     for (int q = g; q < NP; q += RAD_G) {
         const int ib = q % kb, r = q / kb, it = r % kt, ia = r / kt;
-        const double al = a.oexp[oa + ia], at = a.xexp[ot + it], be = a.oexp[ob + ib];
-        // the a and a~ weights without their (2 alpha)^l factors
-        double fa = a.ow[oa + ia], ft = a.xw[ot + it];
-#pragma unroll
-        for (int k = 0; k < LA; ++k) fa *= 2.0 * al;
-#pragma unroll
-        for (int k = 0; k < LT; ++k) ft *= 2.0 * at;
-        aab_accumulate<LA, LT, LB, D>(al + at, be, R2, fa * ft * a.ow[ob + ib], P);
+        aab_accumulate<LA, LT, LB, D>(sE[0][ls][ia] + sE[1][ls][it], sE[2][ls][ib], R2,
+                                      sW[0][ls][ia] * sW[1][ls][it] * sW[2][ls][ib], P);
     }
 #pragma unroll
     for (int m = 1; m < RAD_G; m <<= 1)
